@@ -1,0 +1,189 @@
+"""ctypes binding of the C oracle (``fks_oracle.c``).  Test infrastructure only."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fks_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ENOMEM, EDUPKEY, EBUILD = 0, -1, -2, -3, -4
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDUPKEY: "EDUPKEY", EBUILD: "EBUILD"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle build failed: {_NAMES.get(code, code)}")
+        self.code = code
+
+
+def compile_oracle() -> str:
+    """Compile the C oracle into ``oracle/liboracle.so`` (gcc, plain -O2)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def ensure_built() -> str:
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        compile_oracle()
+    return _LIB
+
+
+_lib = None
+
+
+def liboracle():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(ensure_built())
+        u64, u32, vp, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+        lib.oracle_splitmix.restype = u64
+        lib.oracle_splitmix.argtypes = [u64, u64]
+        lib.oracle_hash.restype = u32
+        lib.oracle_hash.argtypes = [u64, u64, u64, u64]
+        lib.oracle_level1_consts.restype = None
+        lib.oracle_level1_consts.argtypes = [u64, u32, vp]
+        lib.oracle_level2_consts.restype = None
+        lib.oracle_level2_consts.argtypes = [u64, u32, u32, vp]
+        lib.oracle_fingerprint.restype = u64
+        lib.oracle_fingerprint.argtypes = [vp, u64, u64]
+        lib.oracle_build_u64.restype = i32
+        lib.oracle_build_u64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+        lib.oracle_build_bytes.restype = i32
+        lib.oracle_build_bytes.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+        lib.oracle_lookup_u64.restype = i32
+        lib.oracle_lookup_u64.argtypes = [vp, vp, u64, vp, vp, u32]
+        lib.oracle_lookup_bytes.restype = i32
+        lib.oracle_lookup_bytes.argtypes = [vp, vp, vp, u64, vp, vp, u32]
+        lib.oracle_info.restype = None
+        lib.oracle_info.argtypes = [vp, vp]
+        lib.oracle_export.restype = None
+        lib.oracle_export.argtypes = [vp, vp, vp]
+        lib.oracle_free.restype = None
+        lib.oracle_free.argtypes = [vp]
+        lib.oracle_batch_seed.restype = u64
+        lib.oracle_batch_seed.argtypes = [u64, u64]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data if a.size else 0
+
+
+def splitmix(sigma: int, i: int) -> int:
+    return int(liboracle().oracle_splitmix(sigma, i))
+
+
+def hash32(a0: int, a1: int, b: int, x: int) -> int:
+    return int(liboracle().oracle_hash(a0, a1, b, x))
+
+
+def level1_consts(sigma: int, r: int):
+    out = np.zeros(4, np.uint64)
+    liboracle().oracle_level1_consts(sigma, r, _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def level2_consts(sigma: int, r: int, t: int):
+    out = np.zeros(3, np.uint64)
+    liboracle().oracle_level2_consts(sigma, r, t, _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def fingerprint(data: bytes, beta: int) -> int:
+    buf = np.frombuffer(data, np.uint8) if data else np.zeros(1, np.uint8)
+    return int(liboracle().oracle_fingerprint(_ptr(buf), len(data), beta))
+
+
+def batch_seed(batch_sigma: int, m: int) -> int:
+    return int(liboracle().oracle_batch_seed(batch_sigma, m))
+
+
+INFO_FIELDS = ("n", "S", "r", "T", "c", "kind", "beta", "a0", "a1", "a2",
+               "rejected_size", "rejected_space", "rejected_exhausted", "level2_trials")
+
+
+class OracleMap:
+    """A map built by the C oracle; owns the C object."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        info = np.zeros(len(INFO_FIELDS), np.uint64)
+        liboracle().oracle_info(self._h, _ptr(info))
+        self.info = {k: int(v) for k, v in zip(INFO_FIELDS, info)}
+        self.n, self.S, self.r = self.info["n"], self.info["S"], self.info["r"]
+        self.kind = "u64" if self.info["kind"] == 0 else "bytes"
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            liboracle().oracle_free(h)
+            self._h = None
+
+    def export(self):
+        """(header u8[16*ceil(n/8)], slots u8[16*S]) exactly as the oracle laid them out."""
+        ng = (self.n + 7) // 8
+        header = np.zeros(16 * ng, np.uint8)
+        slots = np.zeros(16 * self.S, np.uint8)
+        liboracle().oracle_export(self._h, _ptr(header), _ptr(slots))
+        return header, slots
+
+    def lookup(self, queries: np.ndarray, missing: int = 0xFFFFFFFF):
+        q = np.ascontiguousarray(queries, np.uint64)
+        vals = np.zeros(q.size, np.uint32)
+        found = np.zeros(q.size, np.uint8)
+        rc = liboracle().oracle_lookup_u64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
+        if rc:
+            raise OracleError(rc)
+        return vals, found
+
+    def lookup_bytes(self, offsets: np.ndarray, data: np.ndarray, missing: int = 0xFFFFFFFF):
+        off = np.ascontiguousarray(offsets, np.int64)
+        buf = np.ascontiguousarray(data, np.uint8)
+        if buf.size == 0:
+            buf = np.zeros(1, np.uint8)
+        m = off.size - 1
+        vals = np.zeros(m, np.uint32)
+        found = np.zeros(m, np.uint8)
+        rc = liboracle().oracle_lookup_bytes(self._h, _ptr(off), _ptr(buf), m, _ptr(vals),
+                                             _ptr(found), missing)
+        if rc:
+            raise OracleError(rc)
+        return vals, found
+
+
+def build_u64(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int = 64,
+              R: int = 16) -> OracleMap:
+    k = np.ascontiguousarray(keys, np.uint64)
+    v = np.ascontiguousarray(vals, np.uint32)
+    assert k.size == v.size
+    h = ctypes.c_void_p()
+    rc = liboracle().oracle_build_u64(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
+    if rc:
+        raise OracleError(rc)
+    return OracleMap(h.value)
+
+
+def build_bytes(offsets: np.ndarray, data: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4,
+                T: int = 64, R: int = 16) -> OracleMap:
+    off = np.ascontiguousarray(offsets, np.int64)
+    buf = np.ascontiguousarray(data, np.uint8)
+    if buf.size == 0:
+        buf = np.zeros(1, np.uint8)
+    v = np.ascontiguousarray(vals, np.uint32)
+    n = off.size - 1
+    assert v.size == n
+    h = ctypes.c_void_p()
+    rc = liboracle().oracle_build_bytes(_ptr(off), _ptr(buf), _ptr(v), n, sigma, c, T, R,
+                                        ctypes.byref(h))
+    if rc:
+        raise OracleError(rc)
+    return OracleMap(h.value)

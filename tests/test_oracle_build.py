@@ -1,0 +1,251 @@
+"""Pins for the oracle's construction and lookup.
+
+What fixes the expected results here is independent of the oracle's own code:
+  * dictionary semantics (Python dict / numpy set membership) for every lookup;
+  * the properties of Section 2.2 -- well formed, collision free, the offsets as the
+    exclusive prefix of squared sizes, the histogram as the shape -- and the space bound;
+  * make_2's first-success rule, re-checked by brute force;
+  * the paper's own flattened sortless construction (Section 2.5) run as a second
+    formulation, which must pick the same trial index for every bucket;
+  * the expected statistics of Section 2.3's analysis (bucket sizes ~ Poisson(1),
+    sum of squares ~ 2n, at most about 2 trials per bucket);
+  * a pure-Python restatement for tiny inputs (byte-for-byte agreement).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rounds, spec
+from paper_2508_11443_amd import workloads
+from tests import fkscheck
+
+
+def _keys(n, seed, dense=0.0):
+    return workloads.unique_u64(n, seed, dense)
+
+
+@pytest.mark.parametrize("n", list(range(0, 41)) + [63, 64, 65])
+def test_matches_python_restatement_bytewise(n):
+    for sigma in (1, 99):
+        keys = _keys(n, 1000 + n)
+        vals = np.arange(n, dtype=np.uint32)[::-1].copy()
+        m = oracle.build_u64(keys, vals, sigma)
+        ref = spec.build_small([int(k) for k in keys], [int(v) for v in vals], sigma)
+        h, s = m.export()
+        assert (m.r, m.S) == (ref["r"], ref["S"])
+        assert h.tobytes() == spec.pack_header(ref["sizes"], ref["t"])
+        assert s.tobytes() == spec.pack_cells(ref["cells"])
+
+
+@pytest.mark.parametrize("n,dense", [(1, 0), (2, 0), (3, 0), (7, 0), (8, 0), (9, 0), (100, 0.5),
+                                     (1000, 0.5), (4097, 0.0), (1 << 16, 0.5)])
+@pytest.mark.parametrize("sigma", [0, 0x1234567])
+def test_section22_properties(n, dense, sigma):
+    keys = _keys(n, n * 7 + 1, dense)
+    vals = np.arange(n, dtype=np.uint32)
+    m = oracle.build_u64(keys, vals, sigma)
+    h, s = m.export()
+    fkscheck.check_table(keys, vals, sigma, m.r, h, s)
+
+
+@pytest.mark.parametrize("n", [1, 5, 1000, 1 << 15])
+def test_lookup_is_dictionary_semantics(n):
+    keys = _keys(n, 42 + n, 0.5)
+    vals = (np.arange(n, dtype=np.uint64) * 2654435761 % (1 << 32)).astype(np.uint32)
+    m = oracle.build_u64(keys, vals, 5)
+    q, _ = workloads.u64_queries(keys, 4 * n, 0.5, 7)
+    d = {int(k): int(v) for k, v in zip(keys, vals)}
+    got_v, got_f = m.lookup(q, missing=0xABCDEF01)
+    exp_f = np.array([int(x) in d for x in q], np.uint8)
+    exp_v = np.array([d.get(int(x), 0xABCDEF01) for x in q], np.uint32)
+    assert (got_f == exp_f).all()
+    assert (got_v == exp_v).all()
+    # adversarial absent keys: neighbours of present keys and the keys of the dense run
+    near = np.concatenate([keys + np.uint64(1), keys ^ np.uint64(1 << 63), keys - np.uint64(1)])
+    near = near[~np.isin(near, keys)]
+    _, f2 = m.lookup(near)
+    assert not f2.any()
+
+
+@pytest.mark.parametrize("n", [10, 777, 5000, 1 << 16])
+def test_same_trials_as_sortless_flattened_rounds(n):
+    keys = _keys(n, 3 * n, 0.5)
+    m = oracle.build_u64(keys, np.zeros(n, np.uint32), 77)
+    _, sizes, t, exhausted = rounds.make1(keys, 77, m.r, 64)
+    _, hs, ht = fkscheck.decode_header(m.export()[0], n)
+    assert exhausted.size == 0
+    assert (sizes == hs[:n]).all()
+    assert (t == ht[:n]).all()
+
+
+def test_input_order_does_not_change_bytes():
+    keys = _keys(5000, 8, 0.3)
+    vals = np.arange(5000, dtype=np.uint32)
+    a = oracle.build_u64(keys, vals, 3)
+    perm = np.random.default_rng(0).permutation(5000)
+    b = oracle.build_u64(keys[perm], vals[perm], 3)
+    ha, sa = a.export()
+    hb, sb = b.export()
+    assert a.r == b.r and (ha == hb).all() and (sa == sb).all()
+
+
+def test_special_cases():
+    m = oracle.build_u64(np.array([123456789], np.uint64), np.array([42], np.uint32), 9)
+    h, s = m.export()
+    assert m.S == 1 and m.r == 0
+    base, sizes, t = fkscheck.decode_header(h, 1)
+    assert base[0] == 0 and sizes[0] == 1 and t[0] == 0
+    ck, cv, ca = fkscheck.decode_cells(s)
+    assert ck[0] == 123456789 and cv[0] == 42 and ca[0] == 0
+    v, f = m.lookup(np.array([123456789, 5], np.uint64), missing=7)
+    assert f.tolist() == [1, 0] and v.tolist() == [42, 7]
+    e = oracle.build_u64(np.zeros(0, np.uint64), np.zeros(0, np.uint32), 9)
+    assert e.n == 0 and e.S == 0
+    v, f = e.lookup(np.array([0, 1, 2**64 - 1], np.uint64), missing=3)
+    assert f.tolist() == [0, 0, 0] and v.tolist() == [3, 3, 3]
+    # singleton buckets always use trial 0 and sit at their bucket's offset
+    keys = _keys(3000, 5)
+    mm = oracle.build_u64(keys, np.arange(3000, dtype=np.uint32), 2)
+    info = fkscheck.check_table(keys, np.arange(3000, dtype=np.uint32), 2, mm.r, *mm.export())
+    assert (info["t"][info["sizes"] <= 1] == 0).all()
+
+
+def test_statistics_of_the_analysis():
+    """Section 2.3 analysis: sizes are Poisson(1)-like, sum of squares ~ 2n, and make_2
+    needs at most about 2 trials per bucket on average."""
+    n = 1 << 18
+    keys = _keys(n, 99, 0.0)
+    m = oracle.build_u64(keys, np.zeros(n, np.uint32), 1)
+    _, sizes, t = fkscheck.decode_header(m.export()[0], n)
+    sizes, t = sizes[:n], t[:n]
+    from math import exp, factorial
+    obs = np.bincount(sizes, minlength=8)[:6].astype(float)
+    exp_ = np.array([n * exp(-1) / factorial(k) for k in range(6)])
+    chi2 = float(((obs - exp_) ** 2 / exp_).sum())
+    assert chi2 < 30, (obs, exp_)
+    assert 1.95 < m.S / n < 2.05
+    s2 = sizes == 2
+    p0 = float(np.mean(t[s2] == 0))
+    assert abs(p0 - 0.75) < 0.01, p0
+    s3 = sizes == 3
+    p3 = float(np.mean(t[s3] == 0))
+    assert abs(p3 - (1 - 1 / 9) * (1 - 2 / 9)) < 0.02, p3
+    trials = (t[sizes >= 2] + 1).mean()
+    assert trials < 2.0, trials
+    assert m.info["level2_trials"] == int((t[sizes >= 2] + 1).sum())
+
+
+def test_dense_run_is_no_worse_than_uniform():
+    """Half the keys one run of consecutive integers: multiply-shift spreads a run like a
+    Weyl sequence, so buckets are at least as even as for uniform keys."""
+    n = 1 << 18
+    keys = _keys(n, 98, 0.5)
+    m = oracle.build_u64(keys, np.zeros(n, np.uint32), 1)
+    _, sizes, t = fkscheck.decode_header(m.export()[0], n)
+    sizes, t = sizes[:n], t[:n]
+    assert m.S / n < 2.05
+    assert (t[sizes >= 2] + 1).mean() < 2.0
+
+
+def test_duplicate_keys_are_reported():
+    keys = _keys(1000, 4)
+    keys[10] = keys[500]
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(keys, np.zeros(1000, np.uint32), 1)
+    assert e.value.code == oracle.EDUPKEY
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(np.array([5, 5], np.uint64), np.zeros(2, np.uint32), 1)
+    assert e.value.code == oracle.EDUPKEY
+    # sixteen copies never fit a bucket: every attempt is rejected for size
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(np.full(16, 9, np.uint64), np.zeros(16, np.uint32), 1)
+    assert e.value.code == oracle.EBUILD
+
+
+def test_forced_rejections_and_retry():
+    keys = _keys(2000, 6)
+    vals = np.arange(2000, dtype=np.uint32)
+    # c = 1 asks for a perfect level one: impossible at this size
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(keys, vals, 1, c=1)
+    assert e.value.code == oracle.EBUILD
+    # one level-two trial: some bucket of size >= 2 fails, level one retries
+    retried = 0
+    for sigma in range(30):
+        m = oracle.build_u64(keys[:40], vals[:40], sigma, T=1, R=1024)
+        retried += m.info["rejected_exhausted"] > 0
+        fkscheck.check_table(keys[:40], vals[:40], sigma, m.r, *m.export(), T=1)
+    assert retried > 0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(keys, vals, 1, T=1, R=1)
+    assert e.value.code == oracle.EBUILD
+    # c = 2 on a mid-sized map rejects some attempts for space and still succeeds
+    found_retry = False
+    for sigma in range(40):
+        mm = oracle.build_u64(keys[:200], vals[:200], sigma, c=2, R=64)
+        fkscheck.check_table(keys[:200], vals[:200], sigma, mm.r, *mm.export(), c=2)
+        found_retry |= mm.info["rejected_space"] > 0
+    assert found_retry
+
+
+def test_invalid_parameters():
+    k = np.arange(4, dtype=np.uint64)
+    v = np.zeros(4, np.uint32)
+    for kw in (dict(c=0), dict(T=0), dict(T=257), dict(R=0), dict(c=17)):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.build_u64(k, v, 1, **kw)
+        assert e.value.code == oracle.EINVAL
+
+
+# ---- byte-string keys (Section 3.1) -----------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 2, 50, 3000])
+def test_string_map(n):
+    off, data = workloads.random_strings(n, 17 + n, 0 if n == 2 else 4, 64)
+    vals = np.arange(n, dtype=np.uint32)
+    m = oracle.build_bytes(off, data, vals, 31)
+    strings = workloads.from_csr(off, data)
+    if n:
+        beta = spec.level1_consts(31, m.r)[3]
+        y = np.array([spec.fingerprint(s, beta) for s in strings], np.uint64)
+        fkscheck.check_table(y, vals, 31, m.r, *m.export(), aux=np.arange(n, dtype=np.uint32))
+    qo, qd, qf, qi = workloads.string_queries(off, data, 2 * n + 10, 0.5, 5)
+    v, f = m.lookup_bytes(qo, qd, missing=0xFFFFFFFF)
+    assert (f == qf).all()
+    assert (v[qf == 1] == qi[qf == 1]).all()
+    assert (v[qf == 0] == 0xFFFFFFFF).all()
+
+
+def test_string_map_needle_context_differs():
+    """The stored keys keep the map's copy of their context; needles come with their own."""
+    off, data = workloads.random_strings(100, 3)
+    m = oracle.build_bytes(off, data, np.arange(100, dtype=np.uint32), 1)
+    strings = workloads.from_csr(off, data)
+    # needles are the same strings at different offsets, with junk around them
+    parts = [b"#" * 3 + s + b"!" for s in strings[::-1]]
+    qoff = np.zeros(101, np.int64)
+    pos = 0
+    bufs = []
+    for i, p in enumerate(parts):
+        bufs.append(p)
+        qoff[i] = pos + 3
+        pos += len(p)
+    qbytes = np.frombuffer(b"".join(bufs), np.uint8)
+    starts = qoff[:100].copy()
+    lens = np.array([len(s) for s in strings[::-1]])
+    # CSR needs contiguous slices: express each needle as [start, start+len)
+    v = np.empty(100, np.uint32)
+    f = np.empty(100, np.uint8)
+    for i in range(100):
+        o = np.array([starts[i], starts[i] + lens[i]], np.int64)
+        vi, fi = m.lookup_bytes(o, qbytes)
+        v[i], f[i] = vi[0], fi[0]
+    assert f.all() and (v == np.arange(100)[::-1]).all()
+
+
+def test_duplicate_strings_are_reported():
+    strings = [b"alpha", b"beta", b"gamma", b"beta"]
+    off, data = workloads.to_csr(strings)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_bytes(off, data, np.zeros(4, np.uint32), 1)
+    assert e.value.code == oracle.EDUPKEY
