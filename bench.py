@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the two-level (FKS) hash map hot path on one MI355X.
+
+One step is the whole path over one batch of synthetic input: build a map from
+2^26 unique uint64 keys (half uniform, half one dense run; values = index) and
+answer 2^26 lookups (50% present keys, 50% uniform absent keys, uniform order),
+then release the map.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: whole-step throughput (keys built + needles answered per
+second), the build and lookup rates on their own, the roofline of the dominant
+kernel (per-launch HIP-event time of the library's own launches, algorithmic
+bytes per launch, MI355X HBM peak 8 TB/s), and the CPU oracle timed on the host
+over the same arrays.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SEED = 0xF00D
+DATA_SEED = 2026
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def src_sha(rel):
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# Which source file holds each kernel (for matching committed counter data).
+KERNEL_SRC = {
+    "fks_lookup_u64": "paper_2508_11443_amd/csrc/lookup.hip",
+    "fks_contains_u64": "paper_2508_11443_amd/csrc/lookup.hip",
+    "fks_lookup_bytes": "paper_2508_11443_amd/csrc/lookup.hip",
+    "fks_hist": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_group": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_search_write": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_scan_reduce": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_scan_down": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_scan_tiles": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_zero_counts": "paper_2508_11443_amd/csrc/build.hip",
+}
+
+
+def algorithmic_bytes(kernel, n, m, S, hit_frac, nonempty_frac):
+    """Bytes one launch must move at minimum, from the algorithm (not the counters).
+    Build kernels process n keys, lookups m needles."""
+    G = (n + 7) // 8
+    if kernel == "fks_lookup_u64":
+        probes2 = hit_frac + (1 - hit_frac) * nonempty_frac   # needles that read a cell
+        return m * (8 + 16 + 16 * probes2 + 4 + 1)
+    if kernel == "fks_contains_u64":
+        probes2 = hit_frac + (1 - hit_frac) * nonempty_frac
+        return m * (8 + 16 + 16 * probes2 + 1)
+    if kernel == "fks_hist":
+        return n * (8 + 1) + G * 4 * 2
+    if kernel == "fks_group":
+        return n * (8 + 4 + 1 + 16) + G * (4 + 8)
+    if kernel == "fks_search_write":
+        return n * 16 + G * (4 + 8 + 16) + S * 16
+    if kernel in ("fks_scan_reduce",):
+        return G * 4
+    if kernel == "fks_scan_down":
+        return G * (4 + 8)
+    if kernel == "fks_zero_counts":
+        return G * 4
+    return None
+
+
+def load_traffic(kernel):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    ent = data.get(kernel)
+    if not ent or kernel not in KERNEL_SRC:
+        return None
+    if ent.get("source_sha") != src_sha(KERNEL_SRC[kernel]):
+        return None          # the kernel changed since the counters were taken
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(keys, vals, q, n, m, budget_s):
+    """The oracle, as it stands, on the host: build + lookups over the same arrays (or a
+    prefix of them when the whole would exceed the time budget)."""
+    import oracle
+    oracle.ensure_built()
+    # size the sample from a small probe so the whole run stays near the budget
+    probe = min(n, 1 << 20)
+    t = time.perf_counter()
+    om = oracle.build_u64(keys[:probe], vals[:probe], SEED)
+    om.lookup(q[:probe])
+    per_item = (time.perf_counter() - t) / (2 * probe)
+    del om
+    ns = int(min(n, max(probe, budget_s / max(per_item, 1e-12) / 2)))
+    ns = 1 << int(np.log2(ns))
+    t = time.perf_counter()
+    om = oracle.build_u64(keys[:ns], vals[:ns], SEED)
+    tb = time.perf_counter() - t
+    t = time.perf_counter()
+    om.lookup(q[:ns])
+    tl = time.perf_counter() - t
+    del om
+    return {"value": round(2 * ns / (tb + tl) / 1e6, 3), "unit": "M(keys+queries)/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"single-threaded C oracle: build of the first {ns} keys + {ns} lookups of the "
+                      f"same workload (build {tb:.2f} s, lookup {tl:.2f} s)",
+            "build_mkeys_per_s": round(ns / tb / 1e6, 3), "lookup_mq_per_s": round(ns / tl / 1e6, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the path shards by bucket range "
+                                   "across GPUs by design, but no multi-GPU run is provided",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2508_11443_amd import fks, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n = m = 1 << args.log2n
+    log(f"generating workload n={n} m={m}")
+    keys = workloads.unique_u64(n, DATA_SEED, dense_fraction=0.5)
+    vals = np.arange(n, dtype=np.uint32)
+    q, expect = workloads.u64_queries(keys, m, 0.5, DATA_SEED + 1)
+    d_keys = torch.from_numpy(keys.view(np.int64)).to(dev)
+    d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(q.view(np.int64)).to(dev)
+    d_expect = torch.from_numpy(expect).to(dev)
+    d_v = torch.empty(m, dtype=torch.int32, device=dev)
+    d_f = torch.empty(m, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        mp = fks.fks_build_u64(d_keys, d_vals, SEED, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        fks.fks_lookup_u64(mp, d_q, d_v, d_f, missing=0xFFFFFFFF, stream=stream)
+        if ev:
+            ev[2].record(stream)
+        return mp
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step().destroy()
+    torch.cuda.synchronize()
+
+    fks.fks_prof_enable(True)
+    fks.fks_prof_reset()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for k in range(args.steps):
+        if last is not None:
+            last.destroy()
+        last = step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fks.fks_prof_enable(False)
+    prof = fks.fks_prof_read()
+    wall = t1 - t0
+    build_ms = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    lookup_ms = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+
+    # the answers of the last step are checked before anything is reported
+    ok = bool(torch.equal(d_f, d_expect))
+    hits = d_expect.bool()
+    ok = ok and bool((d_v[~hits] == -1).all())
+    info = last.info()
+    header, _, _ = (None, None, None)
+    hb = np.zeros(info["header_bytes"], np.uint8)
+    fks.library().fks_export(last.handle, hb.ctypes.data, None, None)
+    sizes_words = hb.reshape(-1, 16)[:, 4:8].copy().view(np.uint32).ravel()
+    nib = (sizes_words[:, None] >> (4 * np.arange(8, dtype=np.uint32))[None, :]) & 15
+    nonempty_frac = float((nib.ravel()[:n] > 0).mean())
+    last.destroy()
+    if not ok:
+        log("lookup results differ from the expected answers")
+
+    hit_frac = float(expect.mean())
+    S = info["S"]
+    per_kernel = {}
+    for name, (launches, ms) in prof.items():
+        avg = ms / max(launches, 1)
+        ab = algorithmic_bytes(name, n, m, S, hit_frac, nonempty_frac)
+        per_kernel[name] = {"launches": launches, "avg_ms": round(avg, 4),
+                            "gbs": round(ab / (avg * 1e-3) / 1e9, 1) if ab else None}
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    dom_launches, dom_ms = prof[dom]
+    dom_avg_s = dom_ms / dom_launches * 1e-3
+    dom_bytes = algorithmic_bytes(dom, n, m, S, hit_frac, nonempty_frac)
+    achieved = dom_bytes / dom_avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom), "kernel": dom,
+                "algorithmic_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(dom_avg_s * 1e3, 4)}
+
+    ms_per_step = wall / args.steps * 1e3
+    value = (n + m) / (wall / args.steps) / 1e6
+    build_rate = n / (build_ms * 1e-3) / 1e6
+    lookup_rate = m / (lookup_ms * 1e-3) / 1e6
+    build_alg = n * (12 + 2) + S * 16
+    lookup_alg = algorithmic_bytes("fks_lookup_u64", n, m, S, hit_frac, nonempty_frac)
+    out = {
+        "metric": "build Mkeys/s + lookup Mqueries/s (uint64, 2^26), %HBM peak; serve p50/p99",
+        "value": round(value, 3),
+        "unit": "M(keys built + queries answered)/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "single map: 2^26 unique uint64 keys (half uniform, half one dense run), "
+                               "uint32 values = index; 2^26 lookups, 50% hits, uniform order",
+                   "n": n, "queries": m, "seed": SEED, "data_seed": DATA_SEED, "parallelism": "single-gpu"},
+        "build_mkeys_per_s": round(build_rate, 2),
+        "lookup_mqueries_per_s": round(lookup_rate, 2),
+        "build_ms": round(build_ms, 4), "lookup_ms": round(lookup_ms, 4),
+        "build_pct_hbm": round(100 * build_alg / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+        "lookup_pct_hbm": round(100 * lookup_alg / (lookup_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+        "table": {"S_over_n": round(S / n, 4), "r": info["r"], "max_t": info["max_t"],
+                  "nonempty_bucket_frac": round(nonempty_frac, 4)},
+        "answers_checked": ok,
+        "roofline": roofline,
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(keys, vals, q, n, m, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * fks.h -- C ABI of a static two-level (Fredman-Komlos-Szemeredi) hash map
+ * built and queried on an AMD Instinct MI355X (gfx950).
+ *
+ * The operations are the map interface of Section 3.2 (Figure 2):
+ *   from_array_nodup : ctx -> [n](key, v) -> map      (fks_build_*)
+ *   lookup           : ctx -> key -> map -> opt v      (fks_lookup_*)
+ * with membership testing as a lookup that returns only the "found" flag
+ * (Section 4, the third benchmarked operation).  The map is the hash set
+ * construction of Section 2.2 extended to a map by storing each value beside
+ * its key: g k = hash(const) k mod n picks a bucket, the bucket's own level-two
+ * function places the key in its private block of s^2 cells, the blocks lie at
+ * the exclusive prefix sum of the squared bucket sizes, and a key is found iff
+ * the cell it hashes to holds it.  Keys are 64-bit integers or byte strings;
+ * a string key is a slice of a byte context (Section 3.1): the map keeps its
+ * own copy of the context of its keys, and every needle batch brings its own.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HBM of the current device);
+ *     pointers named h_* are host pointers.  Inputs are borrowed for the call
+ *     only; the library never keeps them.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Builds are ordered on the stream and synchronise the host with it
+ *     (twice per level-one attempt: once to read the table size, once to
+ *     read the level-two outcome).  Lookups are fully asynchronous.
+ *   - Return value 0 (FKS_OK) is success; negative values are the FKS_E*
+ *     codes below.  Out-parameters are written only on success.
+ *   - Maps are immutable after their build and may be read by any number of
+ *     concurrent lookups, on any streams of the device they were built on.
+ *   - Layout of a built table (what fks_export returns, and what the oracle
+ *     reproduces byte for byte):
+ *       header: ceil(n/8) records of 16 bytes, one per group of 8 buckets:
+ *               u32 slot base of the group, u32 sizes (4 bits per bucket,
+ *               bucket 8g+k in bits 4k..4k+3), u8 trial index t[8];
+ *       cells : S records of 16 bytes: u64 key, u32 value, u32 aux
+ *               (aux = 0 for integer keys, the key's index for string keys;
+ *               the key word of a string map is the string's fingerprint).
+ */
+#ifndef FKS_H
+#define FKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define FKS_OK        0
+#define FKS_EINVAL   (-1)  /* bad argument: NULL pointer, n >= 2^30, c*n >= 2^32,
+                              parameter out of range, offsets not monotone,
+                              wrong key kind for the map */
+#define FKS_ENOMEM   (-2)  /* device allocation failed */
+#define FKS_EDUPKEY  (-3)  /* the no-duplicates contract of from_array_nodup was
+                              broken: a bucket that no level-two trial could
+                              separate holds two equal keys */
+#define FKS_EBUILD   (-4)  /* every level-one attempt was rejected */
+#define FKS_EHIP     (-5)  /* a HIP runtime call failed; see fks_last_hip_error */
+
+/* ---- parameters ---------------------------------------------------------
+ * c : space budget; a level-one attempt is kept only if the table has at
+ *     most c*n cells (default 4, range 1..16; Section 2.3 analysis: the
+ *     expected size is about 2n).
+ * T : level-two trials per bucket before the level-one attempt is rejected
+ *     (default 64, range 1..256; make_2 of Section 2.3 retries without bound,
+ *     expected at most 2 trials).
+ * R : level-one attempts before FKS_EBUILD (default 16, range 1..1024).
+ * Attempts also reject any bucket of more than 15 keys.                     */
+typedef struct fks_params {
+    uint32_t c;
+    uint32_t T;
+    uint32_t R;
+    uint32_t reserved;   /* must be 0 */
+} fks_params;
+
+typedef struct fks_map fks_map;       /* opaque; owns all of its device memory */
+
+typedef struct fks_map_info {
+    uint64_t n;           /* number of keys */
+    uint64_t S;           /* number of cells */
+    uint64_t header_bytes;/* 16 * ceil(n/8) */
+    uint64_t slot_bytes;  /* 16 * S */
+    uint64_t ctx_bytes;   /* bytes of the copied string context (0 for integer keys) */
+    uint64_t seed;        /* sigma */
+    uint32_t r;           /* accepted level-one attempt */
+    uint32_t kind;        /* 0 = uint64 keys, 1 = byte-string keys */
+    uint32_t c, T, R;
+    uint32_t max_t;       /* largest trial index used by any bucket */
+    uint64_t device_bytes;/* device memory the map holds */
+} fks_map_info;
+
+/* Fill *p with the defaults {4, 64, 16, 0}. */
+void fks_params_default(fks_params* p);
+
+/*
+ * from_array_nodup for 64-bit keys (Section 2.2 construction, Section 2.3
+ * make_1/make_2, built data-parallel as in Sections 2.4-2.5).
+ *   d_keys : n distinct uint64 keys (device).
+ *   d_vals : n uint32 values (device); value i belongs to key i.
+ *   n      : 0 <= n < 2^30; n = 0 builds the empty map.
+ *   seed   : sigma, the seed of the map's random stream (the `random` of
+ *            Figure 1); the table is a pure function of (keys as a set,
+ *            values, seed, params).
+ *   params : NULL for defaults.
+ *   out    : receives the new map (release with fks_destroy).
+ * Errors: FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY, FKS_EBUILD, FKS_EHIP.
+ */
+int fks_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint64_t seed,
+                  const fks_params* params, void* stream, fks_map** out);
+
+/*
+ * from_array_nodup for byte-string keys (Section 3.1 contexts, Section 3.3.1
+ * slices).  Key i is bytes [d_offsets[i], d_offsets[i+1]) of d_bytes (CSR;
+ * a string may be empty).  Offsets must be non-decreasing, d_offsets[0] >= 0
+ * and d_offsets[n] <= nbytes.  The map copies d_offsets (n+1 int64) and the
+ * first nbytes of d_bytes.  Each level-one attempt fingerprints every string
+ * (Horner over 32-bit little-endian words mod 2^61-1, seeded with the byte
+ * length) and runs the integer construction on the fingerprints; distinct
+ * strings with equal fingerprints force a new attempt with a new base.
+ * Errors: as fks_build_u64; FKS_EDUPKEY when two keys are equal strings.
+ */
+int fks_build_bytes(const int64_t* d_offsets, const uint8_t* d_bytes, uint64_t nbytes,
+                    const uint32_t* d_vals, uint64_t n, uint64_t seed,
+                    const fks_params* params, void* stream, fks_map** out);
+
+/*
+ * lookup (Figure 2) for m integer needles: d_vals_out[i] = value of
+ * d_queries[i] and d_found_out[i] = 1 if the key is in the map, else
+ * d_vals_out[i] = missing and d_found_out[i] = 0.  At most two dependent
+ * table reads per needle.  Either output may be NULL to skip it.
+ * Errors: FKS_EINVAL (NULL map/queries with m > 0, string map), FKS_EHIP.
+ */
+int fks_lookup_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m,
+                   uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, void* stream);
+
+/* Membership only (Section 4): d_found_out[i] = 1 iff d_queries[i] is a key. */
+int fks_contains_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m,
+                     uint8_t* d_found_out, void* stream);
+
+/*
+ * lookup for m string needles given in their own context (Section 3.1: the
+ * needle's context differs from the map's): needle i is bytes
+ * [d_q_offsets[i], d_q_offsets[i+1]) of d_q_bytes.  A hit needs equal
+ * fingerprints and then equal bytes (a third read, of the stored string).
+ */
+int fks_lookup_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
+                     uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
+                     void* stream);
+
+int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
+                       uint64_t m, uint8_t* d_found_out, void* stream);
+
+/* Sizes and build outcome of a map. */
+int fks_info(const fks_map* map, fks_map_info* info);
+
+/*
+ * Copy the table to host memory: h_header (info.header_bytes), h_slots
+ * (info.slot_bytes), optionally h_consts (3*T uint64: the level-two triples
+ * of the accepted attempt).  Any pointer may be NULL.  Synchronous.
+ */
+int fks_export(const fks_map* map, void* h_header, void* h_slots, uint64_t* h_consts);
+
+/* Release a map and its device memory.  NULL is ignored.  The caller must
+   make sure no lookup on the map is still running. */
+void fks_destroy(fks_map* map);
+
+/* Text of an error code. */
+const char* fks_strerror(int code);
+
+/* The last HIP error code seen by the calling thread (hipError_t as int). */
+int fks_last_hip_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int fks_version(void);
+
+/* ---- kernel timing ------------------------------------------------------
+ * When enabled, every kernel the library launches is bracketed by two HIP
+ * events recorded on the stream it runs on; fks_prof_read folds the finished
+ * ones into per-kernel totals (it waits for pending events).  Process-wide,
+ * thread-safe; off by default.                                              */
+typedef struct fks_prof_entry {
+    char name[40];        /* kernel name */
+    uint64_t launches;    /* timed launches since the last reset */
+    double total_ms;      /* summed event time of those launches */
+} fks_prof_entry;
+
+int fks_prof_enable(int on);
+void fks_prof_reset(void);
+/* Writes up to max_entries entries and returns how many it wrote; with
+   out == NULL returns the number of kernels with totals. */
+int fks_prof_read(fks_prof_entry* out, int max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKS_H */

@@ -1,0 +1,130 @@
+// Host-side plumbing of the FKS library: error codes, device memory, map
+// introspection, export and release.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "fks_internal.hpp"
+
+namespace fks {
+
+static thread_local int g_last_hip_error = 0;
+
+void set_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
+
+int hip_fail(hipError_t e) {
+    g_last_hip_error = (int)e;
+    if (e == hipErrorOutOfMemory) return FKS_ENOMEM;
+    return FKS_EHIP;
+}
+
+static std::once_flag g_pool_once[64];
+
+static void configure_pool(int dev) {
+    // keep freed stream-ordered blocks cached in the pool instead of returning
+    // them to the driver at every synchronisation
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t threshold = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+    }
+}
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 16;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], configure_pool, dev);
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+}  // namespace fks
+
+extern "C" {
+
+void fks_params_default(fks_params* p) {
+    if (!p) return;
+    p->c = 4;
+    p->T = 64;
+    p->R = 16;
+    p->reserved = 0;
+}
+
+const char* fks_strerror(int code) {
+    switch (code) {
+        case FKS_OK: return "ok";
+        case FKS_EINVAL: return "invalid argument";
+        case FKS_ENOMEM: return "out of device memory";
+        case FKS_EDUPKEY: return "duplicate keys in from_array_nodup input";
+        case FKS_EBUILD: return "every level-one attempt was rejected";
+        case FKS_EHIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+int fks_last_hip_error(void) { return fks::g_last_hip_error; }
+
+int fks_version(void) { return 10000; }
+
+int fks_info(const fks_map* map, fks_map_info* info) {
+    if (!map || !info) return FKS_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n = map->n;
+    info->S = map->S;
+    info->header_bytes = 16 * ((map->n + 7) / 8);
+    info->slot_bytes = 16 * map->S;
+    info->ctx_bytes = map->ctx_nbytes;
+    info->seed = map->seed;
+    info->r = map->r;
+    info->kind = map->kind;
+    info->c = map->c;
+    info->T = map->T;
+    info->R = map->R;
+    info->max_t = map->max_t;
+    info->device_bytes = map->device_bytes;
+    return FKS_OK;
+}
+
+int fks_export(const fks_map* map, void* h_header, void* h_slots, uint64_t* h_consts) {
+    if (!map) return FKS_EINVAL;
+    int prev = 0;
+    FKS_HIP(hipGetDevice(&prev));
+    FKS_HIP(hipSetDevice(map->device));
+    FKS_HIP(hipDeviceSynchronize());
+    uint64_t hb = 16 * ((map->n + 7) / 8);
+    if (h_header && hb) FKS_HIP(hipMemcpy(h_header, map->header, hb, hipMemcpyDeviceToHost));
+    if (h_slots && map->S) FKS_HIP(hipMemcpy(h_slots, map->slots, 16 * map->S, hipMemcpyDeviceToHost));
+    if (h_consts) FKS_HIP(hipMemcpy(h_consts, map->C, sizeof(fks::Triple) * map->T, hipMemcpyDeviceToHost));
+    FKS_HIP(hipSetDevice(prev));
+    return FKS_OK;
+}
+
+void fks_destroy(fks_map* map) {
+    if (!map) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(map->device);
+    // frees are ordered on the null stream, after all work already queued on it
+    fks::dev_free(map->header, nullptr);
+    fks::dev_free(map->slots, nullptr);
+    fks::dev_free(map->C, nullptr);
+    fks::dev_free(map->ctx_off, nullptr);
+    fks::dev_free(map->ctx_bytes, nullptr);
+    (void)hipSetDevice(prev);
+    delete map;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Internal definitions of the FKS library: device arithmetic, table records,
+// the map object and small host helpers.  Everything here is written for
+// gfx950 (CDNA4): wave64, 64 KiB-per-workgroup LDS budget, 32-bit multiply
+// pieces for 64-bit products.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fks.h"
+
+namespace fks {
+
+// ---- fixed readings of the construction -----------------------------------
+// Stream entries reserved per level-one attempt: (a0, a1, b), the string base,
+// and 256 level-two triples.
+constexpr uint32_t kStride = 772;
+constexpr uint32_t kTMax = 256;
+constexpr uint32_t kSMax = 15;            // largest accepted bucket (4-bit size field)
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kP61 = (1ull << 61) - 1;
+
+struct Triple {
+    uint64_t a0, a1, b;
+};
+
+// 16-byte header record of a group of 8 buckets.
+struct alignas(16) Group {
+    uint32_t base;    // first cell of the group
+    uint32_t sizes;   // 4 bits per bucket
+    uint32_t t_lo;    // trial index of buckets 0..3 (one byte each)
+    uint32_t t_hi;    // trial index of buckets 4..7
+};
+
+// 16-byte cell.
+struct alignas(16) Cell {
+    uint64_t key;
+    uint32_t val;
+    uint32_t aux;
+};
+
+// ---- SplitMix64 (Steele, Lea & Flood 2014), counter based --------------------
+__host__ __device__ inline uint64_t sm_fin(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm_out(uint64_t sigma, uint64_t i) {
+    return sm_fin(sigma + (i + 1) * kGamma);
+}
+__host__ __device__ inline Triple level1_triple(uint64_t sigma, uint32_t r) {
+    uint64_t b = (uint64_t)r * kStride;
+    return Triple{sm_out(sigma, b), sm_out(sigma, b + 1), sm_out(sigma, b + 2)};
+}
+__host__ __device__ inline uint64_t level1_beta(uint64_t sigma, uint32_t r) {
+    return 1 + sm_out(sigma, (uint64_t)r * kStride + 3) % (kP61 - 1);
+}
+__host__ __device__ inline Triple level2_triple(uint64_t sigma, uint32_t r, uint32_t t) {
+    uint64_t b = (uint64_t)r * kStride + 4 + 3ull * t;
+    return Triple{sm_out(sigma, b), sm_out(sigma, b + 1), sm_out(sigma, b + 2)};
+}
+
+// ---- Thorup's vector multiply-shift, w = 32, 64-bit accumulator -------------
+// ((a0*lo + a1*hi + b) mod 2^64) >> 32, written as two 32x32+64 multiply-adds
+// and two 32-bit low multiplies for the upper halves of a0 and a1.
+__host__ __device__ inline uint32_t mshash(uint64_t a0, uint64_t a1, uint64_t b, uint64_t x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    uint64_t t = (uint64_t)(uint32_t)a0 * lo + b;
+    t = (uint64_t)(uint32_t)a1 * hi + t;
+    return (uint32_t)(t >> 32) + (uint32_t)(a0 >> 32) * lo + (uint32_t)(a1 >> 32) * hi;
+}
+__host__ __device__ inline uint32_t mshash(const Triple& c, uint64_t x) {
+    return mshash(c.a0, c.a1, c.b, x);
+}
+
+// ---- exact 32-bit remainder by a runtime divisor ------------------------------
+// Lemire, Kaser & Kurz, "Faster remainder by direct computation" (2019):
+// with M = floor((2^64-1)/d) + 1, a mod d = ((M*a mod 2^64) * d) >> 64 for every
+// 32-bit a and d >= 1.
+__host__ __device__ inline uint64_t fastmod_magic(uint32_t d) {
+    return 0xFFFFFFFFFFFFFFFFull / d + 1;
+}
+__host__ __device__ inline uint32_t fastmod(uint32_t a, uint64_t M, uint32_t d) {
+    uint64_t low = (uint64_t)(uint32_t)M * a;
+    low += (uint64_t)((uint32_t)(M >> 32) * a) << 32;
+    // high 64 bits of the 96-bit product low * d
+    uint64_t mid = (uint64_t)(uint32_t)(low >> 32) * d + (uint32_t)(((uint64_t)(uint32_t)low * d) >> 32);
+    return (uint32_t)(mid >> 32);
+}
+
+// ---- string fingerprint: Horner over 32-bit words mod 2^61-1 ----------------
+__host__ __device__ inline uint64_t mulmod61(uint64_t a, uint64_t b) {
+    // a, b < 2^61: the 122-bit product folded twice (2^61 == 1 mod p)
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint64_t lo = a * b;
+    uint64_t hi = __umul64hi(a, b);
+#else
+    unsigned __int128 p = (unsigned __int128)a * b;
+    uint64_t lo = (uint64_t)p, hi = (uint64_t)(p >> 64);
+#endif
+    uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
+    r = (r & kP61) + (r >> 61);
+    return r >= kP61 ? r - kP61 : r;
+}
+__host__ __device__ inline uint64_t addmod61(uint64_t a, uint64_t w) {
+    uint64_t r = a + w;            // a < 2^61, w < 2^32: no overflow
+    r = (r & kP61) + (r >> 61);
+    return r >= kP61 ? r - kP61 : r;
+}
+
+// ---- header helpers ---------------------------------------------------------
+__host__ __device__ inline uint32_t nib(uint32_t sizes, uint32_t k) {
+    return (sizes >> (4 * k)) & 15u;
+}
+// sum of squared sizes of buckets 0..k-1 of a group
+__host__ __device__ inline uint32_t prefix_sq(uint32_t sizes, uint32_t k) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 7; ++i) {
+        uint32_t s = nib(sizes, i);
+        acc += (i < k) ? s * s : 0u;
+    }
+    return acc;
+}
+__host__ __device__ inline uint32_t prefix_cnt(uint32_t sizes, uint32_t k) {
+    // keep the nibbles below bucket k, then add them up pairwise
+    uint32_t m = (k == 0) ? 0u : (0xFFFFFFFFu >> (32 - 4 * k));
+    uint32_t v = sizes & m;
+    v = (v & 0x0F0F0F0Fu) + ((v >> 4) & 0x0F0F0F0Fu);
+    v = v + (v >> 8);
+    v = v + (v >> 16);
+    return v & 0xFFu;
+}
+__host__ __device__ inline uint32_t group_t(const Group& g, uint32_t k) {
+    uint32_t w = k < 4 ? g.t_lo : g.t_hi;
+    return (w >> (8 * (k & 3))) & 0xFFu;
+}
+
+}  // namespace fks
+
+// ---- the map object (host side) ---------------------------------------------
+struct fks_map {
+    uint32_t kind;        // 0 u64, 1 bytes
+    int device;
+    uint64_t n, S, seed;
+    uint32_t r, c, T, R, max_t;
+    fks::Triple A;        // level-one triple of the accepted attempt
+    uint64_t beta;        // string base of the accepted attempt
+    uint64_t magic_n;     // fastmod magic of n
+    fks::Group* header;   // ceil(n/8)
+    fks::Cell* slots;     // S
+    fks::Triple* C;       // T level-two triples (device)
+    int64_t* ctx_off;     // bytes maps: copy of the offsets (n+1)
+    uint8_t* ctx_bytes;   // bytes maps: copy of the context
+    uint64_t ctx_nbytes;
+    uint64_t device_bytes;
+};
+
+namespace fks {
+
+// error bookkeeping
+void set_hip_error(hipError_t e);
+int hip_fail(hipError_t e);
+
+// device memory: stream-ordered allocations from the device's default pool,
+// which keeps freed blocks cached for the next build
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// pinned host staging for the small readbacks of a build
+struct Readback {
+    uint64_t S;          // sum of squared sizes of the attempt
+    uint32_t oversize;   // some bucket holds more than 15 keys
+    uint32_t exhausted;  // some bucket ran out of level-two trials
+    uint32_t dup;        // an exhausted bucket holds two equal keys
+    uint32_t bad_input;  // string offsets not monotone / out of range
+    uint32_t max_t;
+    uint32_t pad;
+};
+
+}  // namespace fks
+
+#define FKS_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return fks::hip_fail(e_); \
+    } while (0)

@@ -1,0 +1,222 @@
+// Batched lookup and membership (Figure 2 lookup; Section 4 operations 2 and 3).
+//
+// Per needle: j = hash(A) q mod n selects a bucket; probe 1 reads the 16-byte
+// record of the bucket's group (slot base, the eight 4-bit sizes, the eight
+// trial indices); the bucket's cell is base + sum of the squared sizes before
+// it + hash(C[t]) q mod s^2, with the level-two triples C staged in LDS; probe
+// 2 reads that cell and compares keys (Section 2.2 membership test).  An empty
+// bucket answers "absent" after one probe.  Each thread keeps several needles
+// in flight so that their random probes overlap.
+#include <hip/hip_runtime.h>
+
+#include "fks_internal.hpp"
+#include "prof.hpp"
+
+namespace fks {
+
+constexpr int kLBlock = 256;
+constexpr int kQ = 4;   // needles in flight per thread
+
+__global__ void k_fill_outputs(uint64_t m, uint32_t* __restrict__ vals, uint8_t* __restrict__ found,
+                               uint32_t missing) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (vals) vals[i] = missing;
+        if (found) found[i] = 0;
+    }
+}
+
+template <bool WANT_VALS, bool WANT_FOUND>
+__global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict__ header,
+                                                          const Cell* __restrict__ slots, Triple A,
+                                                          uint64_t magic, uint32_t n,
+                                                          const Triple* __restrict__ Cg, uint32_t T,
+                                                          const uint64_t* __restrict__ q, uint64_t m,
+                                                          uint32_t* __restrict__ vals,
+                                                          uint8_t* __restrict__ found, uint32_t missing) {
+    __shared__ Triple C[kTMax];
+    for (uint32_t t = threadIdx.x; t < T; t += kLBlock) C[t] = Cg[t];
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * kLBlock * kQ;
+    for (uint64_t base = (uint64_t)blockIdx.x * kLBlock * kQ; base < m; base += stride) {
+        uint64_t x[kQ];
+        Group h[kQ];
+        uint32_t kk[kQ];
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * kLBlock;
+            x[k] = i < m ? q[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * kLBlock;
+            const uint32_t j = fastmod(mshash(A, x[k]), magic, n);
+            kk[k] = j & 7u;
+            if (i < m) h[k] = header[j >> 3];
+            else h[k] = Group{0, 0, 0, 0};
+        }
+        Cell c[kQ];
+        uint32_t s[kQ];
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+            s[k] = nib(h[k].sizes, kk[k]);
+            if (s[k]) {
+                const uint32_t s2 = s[k] * s[k];
+                const uint32_t p = h[k].base + prefix_sq(h[k].sizes, kk[k]) +
+                                   mshash(C[group_t(h[k], kk[k])], x[k]) % s2;
+                c[k] = slots[p];
+            } else {
+                c[k] = Cell{~x[k], 0, 0};
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * kLBlock;
+            if (i < m) {
+                const bool hit = s[k] && c[k].key == x[k];
+                if (WANT_VALS) vals[i] = hit ? c[k].val : missing;
+                if (WANT_FOUND) found[i] = hit ? 1 : 0;
+            }
+        }
+    }
+}
+
+// string needles: fingerprint, probe, then compare the stored bytes on a hit
+__device__ inline uint64_t fp_dev(const uint8_t* __restrict__ s, uint64_t len, uint64_t beta) {
+    uint64_t acc = len % kP61;
+    uint64_t full = len / 4;
+    for (uint64_t k = 0; k < full; ++k) {
+        const uint8_t* p = s + 4 * k;
+        uint32_t w = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+        acc = addmod61(mulmod61(acc, beta), w);
+    }
+    uint64_t rest = len - 4 * full;
+    if (rest) {
+        const uint8_t* p = s + 4 * full;
+        uint32_t w = 0;
+        for (uint64_t t = 0; t < rest; ++t) w |= (uint32_t)p[t] << (8 * t);
+        acc = addmod61(mulmod61(acc, beta), w);
+    }
+    return acc;
+}
+
+template <bool WANT_VALS>
+__global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
+    const Group* __restrict__ header, const Cell* __restrict__ slots, Triple A, uint64_t beta,
+    uint64_t magic, uint32_t n, const Triple* __restrict__ Cg, uint32_t T,
+    const int64_t* __restrict__ koff, const uint8_t* __restrict__ kbytes,
+    const int64_t* __restrict__ qoff, const uint8_t* __restrict__ qbytes, uint64_t m,
+    uint32_t* __restrict__ vals, uint8_t* __restrict__ found, uint32_t missing) {
+    __shared__ Triple C[kTMax];
+    for (uint32_t t = threadIdx.x; t < T; t += kLBlock) C[t] = Cg[t];
+    __syncthreads();
+    for (uint64_t i = (uint64_t)blockIdx.x * kLBlock + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * kLBlock) {
+        const int64_t a = qoff[i], b = qoff[i + 1];
+        const uint64_t len = (uint64_t)(b - a);
+        const uint8_t* s = qbytes + a;
+        const uint64_t y = fp_dev(s, len, beta);
+        const uint32_t j = fastmod(mshash(A, y), magic, n);
+        const Group h = header[j >> 3];
+        const uint32_t k = j & 7u;
+        const uint32_t sz = nib(h.sizes, k);
+        bool hit = false;
+        uint32_t v = missing;
+        if (sz) {
+            const uint32_t p = h.base + prefix_sq(h.sizes, k) + mshash(C[group_t(h, k)], y) % (sz * sz);
+            const Cell c = slots[p];
+            if (c.key == y) {
+                const int64_t ka = koff[c.aux], kb = koff[c.aux + 1];
+                if ((uint64_t)(kb - ka) == len) {
+                    const uint8_t* t = kbytes + ka;
+                    bool eq = true;
+                    for (uint64_t q = 0; q < len && eq; ++q) eq = (t[q] == s[q]);
+                    if (eq) {
+                        hit = true;
+                        v = c.val;
+                    }
+                }
+            }
+        }
+        if (WANT_VALS) vals[i] = v;
+        if (found) found[i] = hit ? 1 : 0;
+    }
+}
+
+static unsigned lookup_grid(uint64_t m, uint64_t per_block) {
+    uint64_t g = (m + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+}  // namespace fks
+
+using namespace fks;
+
+extern "C" int fks_lookup_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m, uint32_t* d_vals_out,
+                              uint8_t* d_found_out, uint32_t missing, void* stream) {
+    if (!map || map->kind != 0 || (m && !d_queries)) return FKS_EINVAL;
+    if (m == 0 || (!d_vals_out && !d_found_out)) return FKS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (map->n == 0) {
+        FKS_TIMED("fks_fill_outputs", st, hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, d_vals_out, d_found_out,
+                           missing));
+    } else {
+        const unsigned grid = lookup_grid(m, (uint64_t)kLBlock * kQ);
+        if (d_vals_out && d_found_out)
+            FKS_TIMED("fks_lookup_u64", st, hipLaunchKernelGGL((k_lookup_u64<true, true>), grid, kLBlock, 0, st, map->header, map->slots, map->A,
+                               map->magic_n, (uint32_t)map->n, map->C, map->T, d_queries, m, d_vals_out,
+                               d_found_out, missing));
+        else if (d_vals_out)
+            FKS_TIMED("fks_lookup_u64", st, hipLaunchKernelGGL((k_lookup_u64<true, false>), grid, kLBlock, 0, st, map->header, map->slots, map->A,
+                               map->magic_n, (uint32_t)map->n, map->C, map->T, d_queries, m, d_vals_out,
+                               d_found_out, missing));
+        else
+            FKS_TIMED("fks_contains_u64", st, hipLaunchKernelGGL((k_lookup_u64<false, true>), grid, kLBlock, 0, st, map->header, map->slots, map->A,
+                               map->magic_n, (uint32_t)map->n, map->C, map->T, d_queries, m, d_vals_out,
+                               d_found_out, missing));
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
+extern "C" int fks_contains_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m, uint8_t* d_found_out,
+                                void* stream) {
+    if (!d_found_out && m) return FKS_EINVAL;
+    return fks_lookup_u64(map, d_queries, m, nullptr, d_found_out, 0, stream);
+}
+
+static int lookup_bytes_impl(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes, uint64_t m,
+                             uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, void* stream) {
+    if (!map || map->kind != 1 || (m && (!d_q_offsets || !d_q_bytes))) return FKS_EINVAL;
+    if (m == 0 || (!d_vals_out && !d_found_out)) return FKS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (map->n == 0) {
+        FKS_TIMED("fks_fill_outputs", st, hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, d_vals_out, d_found_out,
+                           missing));
+    } else {
+        const unsigned grid = lookup_grid(m, (uint64_t)kLBlock * 2);
+        if (d_vals_out)
+            FKS_TIMED("fks_lookup_bytes", st, hipLaunchKernelGGL(k_lookup_bytes<true>, grid, kLBlock, 0, st, map->header, map->slots, map->A,
+                               map->beta, map->magic_n, (uint32_t)map->n, map->C, map->T, map->ctx_off,
+                               map->ctx_bytes, d_q_offsets, d_q_bytes, m, d_vals_out, d_found_out, missing));
+        else
+            FKS_TIMED("fks_contains_bytes", st, hipLaunchKernelGGL(k_lookup_bytes<false>, grid, kLBlock, 0, st, map->header, map->slots, map->A,
+                               map->beta, map->magic_n, (uint32_t)map->n, map->C, map->T, map->ctx_off,
+                               map->ctx_bytes, d_q_offsets, d_q_bytes, m, d_vals_out, d_found_out, missing));
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
+extern "C" int fks_lookup_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
+                                uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
+                                void* stream) {
+    return lookup_bytes_impl(map, d_q_offsets, d_q_bytes, m, d_vals_out, d_found_out, missing, stream);
+}
+
+extern "C" int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
+                                  uint64_t m, uint8_t* d_found_out, void* stream) {
+    return lookup_bytes_impl(map, d_q_offsets, d_q_bytes, m, nullptr, d_found_out, 0, stream);
+}

@@ -1,0 +1,272 @@
+"""Thin Python binding of ``libfks.so`` (the C ABI declared in include/fks.h).
+
+Argument marshalling only: every step of a build or a lookup runs in the HIP
+kernels of the library.  Device buffers are torch tensors on a ROCm device
+(torch supplies the memory and the stream); the functions carry the names of
+the C entry points they call.  There is no fallback: if the library is not
+built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfks.so")
+
+FKS_OK, FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY, FKS_EBUILD, FKS_EHIP = 0, -1, -2, -3, -4, -5
+
+
+class FksError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        lib = _load()
+        msg = lib.fks_strerror(code).decode()
+        if code == FKS_EHIP:
+            msg += f" (hipError {lib.fks_last_hip_error()})"
+        super().__init__(f"{what}: {msg}" if what else msg)
+        self.code = code
+
+
+class fks_params(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_uint32), ("T", ctypes.c_uint32), ("R", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class fks_prof_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+class fks_map_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("S", ctypes.c_uint64), ("header_bytes", ctypes.c_uint64),
+                ("slot_bytes", ctypes.c_uint64), ("ctx_bytes", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("r", ctypes.c_uint32), ("kind", ctypes.c_uint32),
+                ("c", ctypes.c_uint32), ("T", ctypes.c_uint32), ("R", ctypes.c_uint32),
+                ("max_t", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _U64, _U32, _I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+SIGNATURES = [
+    ("fks_params_default", None, [_VP]),
+    ("fks_build_u64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_bytes", _I32, [_VP, _VP, _U64, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_lookup_u64", _I32, [_VP, _VP, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_contains_u64", _I32, [_VP, _VP, _U64, _VP, _VP]),
+    ("fks_lookup_bytes", _I32, [_VP, _VP, _VP, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_contains_bytes", _I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    ("fks_info", _I32, [_VP, _VP]),
+    ("fks_export", _I32, [_VP, _VP, _VP, _VP]),
+    ("fks_destroy", None, [_VP]),
+    ("fks_strerror", ctypes.c_char_p, [_I32]),
+    ("fks_last_hip_error", _I32, []),
+    ("fks_version", _I32, []),
+    ("fks_prof_enable", _I32, [_I32]),
+    ("fks_prof_reset", None, []),
+    ("fks_prof_read", _I32, [_VP, _I32]),
+]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _load()
+
+
+def _check(rc: int, what: str):
+    if rc != FKS_OK:
+        raise FksError(rc, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtypes, name):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _u64_types():
+    import torch
+    return (torch.int64, torch.uint64)
+
+
+def _u32_types():
+    import torch
+    return (torch.int32, torch.uint32)
+
+
+def _params(c=None, T=None, R=None):
+    p = fks_params()
+    _load().fks_params_default(ctypes.byref(p))
+    if c is not None:
+        p.c = c
+    if T is not None:
+        p.T = T
+    if R is not None:
+        p.R = R
+    return p
+
+
+class FksMap:
+    """A built map; owns the C handle and releases it with fks_destroy."""
+
+    def __init__(self, handle: int, kind: str):
+        self._h = ctypes.c_void_p(handle)
+        self.kind = kind
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = fks_map_info()
+        _check(_load().fks_info(self._h, ctypes.byref(inf)), "fks_info")
+        return {name: getattr(inf, name) for name, _ in fks_map_info._fields_}
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _load().fks_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fks_build_u64(keys, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+    """from_array_nodup over n uint64 keys (device tensor, int64 or uint64) and uint32 values."""
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and values differ in length")
+    p = _params(c, T, R)
+    out = ctypes.c_void_p()
+    rc = _load().fks_build_u64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
+                               seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
+    _check(rc, "fks_build_u64")
+    return FksMap(out.value, "u64")
+
+
+def fks_build_bytes(offsets, data, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+    """from_array_nodup over n byte-string keys given as CSR (int64 offsets[n+1], uint8 bytes)."""
+    import torch
+    n = offsets.numel() - 1
+    if vals.numel() != n:
+        raise ValueError("keys and values differ in length")
+    p = _params(c, T, R)
+    out = ctypes.c_void_p()
+    rc = _load().fks_build_bytes(_dev(offsets, (torch.int64,), "offsets"),
+                                 _dev(data, (torch.uint8,), "bytes") if data.numel() else None,
+                                 data.numel(), _dev(vals, _u32_types(), "vals"), n,
+                                 seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
+                                 ctypes.byref(out))
+    _check(rc, "fks_build_bytes")
+    return FksMap(out.value, "bytes")
+
+
+def fks_lookup_u64(m: FksMap, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):
+    import torch
+    rc = _load().fks_lookup_u64(m.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
+                                _dev(vals_out, _u32_types(), "vals_out"),
+                                _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                missing & 0xFFFFFFFF, _stream(stream))
+    _check(rc, "fks_lookup_u64")
+
+
+def fks_contains_u64(m: FksMap, queries, found_out, stream=None):
+    import torch
+    rc = _load().fks_contains_u64(m.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
+                                  _dev(found_out, (torch.uint8, torch.bool), "found_out"), _stream(stream))
+    _check(rc, "fks_contains_u64")
+
+
+def fks_lookup_bytes(m: FksMap, q_offsets, q_data, vals_out, found_out, missing: int = 0xFFFFFFFF,
+                     stream=None):
+    import torch
+    rc = _load().fks_lookup_bytes(m.handle, _dev(q_offsets, (torch.int64,), "q_offsets"),
+                                  _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else ctypes.c_void_p(q_offsets.data_ptr()),
+                                  q_offsets.numel() - 1, _dev(vals_out, _u32_types(), "vals_out"),
+                                  _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                  missing & 0xFFFFFFFF, _stream(stream))
+    _check(rc, "fks_lookup_bytes")
+
+
+def fks_contains_bytes(m: FksMap, q_offsets, q_data, found_out, stream=None):
+    import torch
+    rc = _load().fks_contains_bytes(m.handle, _dev(q_offsets, (torch.int64,), "q_offsets"),
+                                    _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else ctypes.c_void_p(q_offsets.data_ptr()),
+                                    q_offsets.numel() - 1, _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                    _stream(stream))
+    _check(rc, "fks_contains_bytes")
+
+
+def fks_info(m: FksMap) -> dict:
+    return m.info()
+
+
+def fks_export(m: FksMap):
+    """Host copies (header uint8[], cells uint8[], level-two triples uint64[T,3]) of a map."""
+    import numpy as np
+    inf = m.info()
+    header = np.zeros(inf["header_bytes"], np.uint8)
+    slots = np.zeros(inf["slot_bytes"], np.uint8)
+    consts = np.zeros((inf["T"], 3), np.uint64)
+    rc = _load().fks_export(m.handle, header.ctypes.data if header.size else None,
+                            slots.ctypes.data if slots.size else None, consts.ctypes.data)
+    _check(rc, "fks_export")
+    return header, slots, consts
+
+
+def fks_destroy(m: FksMap):
+    m.destroy()
+
+
+def fks_version() -> int:
+    return _load().fks_version()
+
+
+def fks_prof_enable(on: bool = True):
+    _load().fks_prof_enable(1 if on else 0)
+
+
+def fks_prof_reset():
+    _load().fks_prof_reset()
+
+
+def fks_prof_read() -> dict:
+    """{kernel name: (launches, total ms)} of the launches timed since the last reset."""
+    lib = _load()
+    cnt = lib.fks_prof_read(None, 0)
+    arr = (fks_prof_entry * max(cnt, 1))()
+    got = lib.fks_prof_read(ctypes.cast(arr, ctypes.c_void_p), cnt)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(got)}
