@@ -173,6 +173,106 @@ int fks_last_hip_error(void);
 /* Library version, major*10000 + minor*100 + patch. */
 int fks_version(void);
 
+/* ---- batches of maps ----------------------------------------------------
+ * One more level of flattening above Section 2.4's buckets: M independent
+ * maps (Section 3.2 notes that maps cannot be array elements, since that
+ * would make arrays irregular) built in one persistent launch.  Map m holds
+ * keys [h_map_offsets[m], h_map_offsets[m+1]) of d_keys / d_vals and is built
+ * exactly as fks_build_u64 would build it with seed = entry m of the
+ * SplitMix64 stream of batch_seed, so its table bytes equal the single-map
+ * build's.  Limits: each map holds at most 65536 keys; c * total keys < 2^40.
+ * Every map owns c * n cells of the batch's cell pool.  A map whose build
+ * fails (FKS_EDUPKEY / FKS_EBUILD, see fks_batch_status) answers every
+ * lookup with "absent"; the call itself still succeeds.
+ *   h_map_offsets : host array of M+1 non-decreasing offsets, first one 0.
+ *   schedule      : 0 = the tuned (or default) schedule for this batch size
+ *                   class; otherwise one of fks_batch_schedules().
+ */
+typedef struct fks_batch fks_batch;
+
+int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_vals, const uint64_t* h_map_offsets,
+                        uint32_t M, uint64_t batch_seed, const fks_params* params, uint32_t schedule,
+                        void* stream, fks_batch** out);
+
+/* Needle i asks map d_map_ids[i] for key d_queries[i]; map ids >= M are
+   answered "absent".  Asynchronous; outputs as fks_lookup_u64. */
+int fks_lookup_batch_u64(const fks_batch* batch, const uint32_t* d_map_ids, const uint64_t* d_queries,
+                         uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
+                         void* stream);
+
+/* Per-map outcome (host arrays of M entries; any may be NULL): status
+   (FKS_OK or an error code), accepted attempt r, cell count S. */
+int fks_batch_status(const fks_batch* batch, int32_t* h_status, uint32_t* h_r, uint32_t* h_S);
+
+/* Sizes of map `index` (returns its status). */
+int fks_batch_info(const fks_batch* batch, uint32_t index, fks_map_info* info);
+
+/* Table of map `index`, laid out as fks_export lays out a single map. */
+int fks_batch_export(const fks_batch* batch, uint32_t index, void* h_header, void* h_slots,
+                     uint64_t* h_consts);
+
+void fks_batch_destroy(fks_batch* batch);
+
+/* Schedules of the batched build: bits 0-1 select 256/512/1024 threads per
+   workgroup, bits 4-7 the workgroups per CU.  fks_batch_schedules lists the
+   valid ones (returns their count; out may be NULL).  fks_batch_set_schedule
+   records the schedule that schedule = 0 uses for batches of the same size
+   class (log2 of M and of the mean map size) in this process. */
+int fks_batch_schedules(uint32_t* out, int max_entries);
+int fks_batch_set_schedule(uint32_t M, uint64_t total_keys, uint32_t schedule);
+
+/* ---- serving --------------------------------------------------------------
+ * A request loop over resident maps (not in the paper; it turns the map of
+ * Sections 2-3 into a service).  Builds are admitted against a device-memory
+ * budget (an estimate of c*n cells per pending build; idle maps are evicted
+ * least recently used first when the budget would be exceeded) and run one at
+ * a time on the server's build stream.  Lookup requests of any size that are
+ * queued while other work runs are coalesced into one multi-request launch on
+ * the lookup stream, replayed from a HIP graph captured per (ring slot, grid
+ * size); so lookups overlap builds on the device.  Results do not depend on
+ * what else is in flight: each request's outputs are those of the same call
+ * made alone.
+ *   Device buffers passed to submit calls must stay valid until the request
+ *   completes (fks_server_poll / fks_server_wait_all).  Lookups against a map
+ *   that failed to build, or was evicted, complete with that error status.
+ *   flags: bit 0 disables graph replay (plain launches).
+ */
+typedef struct fks_server fks_server;
+
+typedef struct fks_server_stats {
+    uint64_t requests, completed;
+    uint64_t lookup_launches;     /* multi-request launches */
+    uint64_t graph_replays;       /* launches replayed from a captured graph */
+    uint64_t graphs_captured;
+    uint64_t coalesced_requests;  /* lookup requests carried by those launches */
+    uint64_t evictions;
+    uint64_t resident_bytes;
+    uint64_t queries_done, keys_built;
+    double span_ms;               /* first submission to last completion */
+    uint32_t resident_maps, pad;
+} fks_server_stats_t;
+
+int fks_server_create(uint64_t budget_bytes, const fks_params* params, uint32_t flags, fks_server** out);
+/* Queue a build; *map_id names the future map at once (lookups may be queued
+   against it before it is built). */
+int fks_server_submit_build(fks_server* srv, const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n,
+                            uint64_t seed, uint64_t* req_id, uint32_t* map_id);
+int fks_server_submit_lookup(fks_server* srv, uint32_t map_id, const uint64_t* d_queries, uint64_t m,
+                             uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, uint64_t* req_id);
+/* *done = 1 once finished; *latency_ms = completion - submission (host clock). */
+int fks_server_poll(fks_server* srv, uint64_t req_id, int* done, int* status, double* latency_ms);
+int fks_server_wait_all(fks_server* srv);
+/* Per-request submission and completion times (ms, host steady clock), kind
+   (0 build, 1 lookup) and status, for requests 0..max_entries-1; returns the
+   count written.  Any array may be NULL. */
+int fks_server_latencies(fks_server* srv, double* h_submit_ms, double* h_done_ms, int32_t* h_kind,
+                         int32_t* h_status, uint64_t max_entries);
+int fks_server_stats(fks_server* srv, fks_server_stats_t* stats);
+/* The resident map behind map_id, or NULL (not built yet, failed, evicted). */
+const fks_map* fks_server_map(fks_server* srv, uint32_t map_id);
+/* Waits for every submitted request, then releases the server and its maps. */
+void fks_server_destroy(fks_server* srv);
+
 /* ---- kernel timing ------------------------------------------------------
  * When enabled, every kernel the library launches is bracketed by two HIP
  * events recorded on the stream it runs on; fks_prof_read folds the finished

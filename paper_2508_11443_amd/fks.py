@@ -62,6 +62,23 @@ SIGNATURES = [
     ("fks_strerror", ctypes.c_char_p, [_I32]),
     ("fks_last_hip_error", _I32, []),
     ("fks_version", _I32, []),
+    ("fks_build_batch_u64", _I32, [_VP, _VP, _VP, _U32, _U64, _VP, _U32, _VP, ctypes.POINTER(_VP)]),
+    ("fks_lookup_batch_u64", _I32, [_VP, _VP, _VP, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_batch_status", _I32, [_VP, _VP, _VP, _VP]),
+    ("fks_batch_info", _I32, [_VP, _U32, _VP]),
+    ("fks_batch_export", _I32, [_VP, _U32, _VP, _VP, _VP]),
+    ("fks_batch_destroy", None, [_VP]),
+    ("fks_batch_set_schedule", _I32, [_U32, _U64, _U32]),
+    ("fks_batch_schedules", _I32, [_VP, _I32]),
+    ("fks_server_create", _I32, [_U64, _VP, _U32, ctypes.POINTER(_VP)]),
+    ("fks_server_submit_build", _I32, [_VP, _VP, _VP, _U64, _U64, _VP, _VP]),
+    ("fks_server_submit_lookup", _I32, [_VP, _U32, _VP, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_server_poll", _I32, [_VP, _U64, _VP, _VP, _VP]),
+    ("fks_server_wait_all", _I32, [_VP]),
+    ("fks_server_latencies", _I32, [_VP, _VP, _VP, _VP, _VP, _U64]),
+    ("fks_server_stats", _I32, [_VP, _VP]),
+    ("fks_server_map", _VP, [_VP, _U32]),
+    ("fks_server_destroy", None, [_VP]),
     ("fks_prof_enable", _I32, [_I32]),
     ("fks_prof_reset", None, []),
     ("fks_prof_read", _I32, [_VP, _I32]),
@@ -270,3 +287,180 @@ def fks_prof_read() -> dict:
     arr = (fks_prof_entry * max(cnt, 1))()
     got = lib.fks_prof_read(ctypes.cast(arr, ctypes.c_void_p), cnt)
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(got)}
+
+
+# ---- batches of maps -------------------------------------------------------------
+
+class FksBatch:
+    """M independent maps built in one persistent launch; owns the C handle."""
+
+    def __init__(self, handle: int, M: int):
+        self._h = ctypes.c_void_p(handle)
+        self.M = M
+
+    @property
+    def handle(self):
+        return self._h
+
+    def status(self):
+        import numpy as np
+        st = np.zeros(self.M, np.int32)
+        r = np.zeros(self.M, np.uint32)
+        S = np.zeros(self.M, np.uint32)
+        _check(_load().fks_batch_status(self._h, st.ctypes.data, r.ctypes.data, S.ctypes.data),
+               "fks_batch_status")
+        return st, r, S
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _load().fks_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fks_build_batch_u64(keys, vals, map_offsets, batch_seed: int, c=None, T=None, R=None, schedule: int = 0,
+                        stream=None) -> FksBatch:
+    """Build M maps: map m holds keys[map_offsets[m]:map_offsets[m+1]] (host offsets, M+1 entries)."""
+    import numpy as np
+    off = np.ascontiguousarray(map_offsets, np.uint64)
+    M = off.size - 1
+    p = _params(c, T, R)
+    out = ctypes.c_void_p()
+    rc = _load().fks_build_batch_u64(_dev(keys, _u64_types(), "keys") if keys.numel() else None,
+                                     _dev(vals, _u32_types(), "vals") if vals.numel() else None,
+                                     off.ctypes.data, M, batch_seed & ((1 << 64) - 1), ctypes.byref(p),
+                                     schedule, _stream(stream), ctypes.byref(out))
+    _check(rc, "fks_build_batch_u64")
+    return FksBatch(out.value, M)
+
+
+def fks_lookup_batch_u64(b: FksBatch, map_ids, queries, vals_out, found_out, missing: int = 0xFFFFFFFF,
+                         stream=None):
+    import torch
+    rc = _load().fks_lookup_batch_u64(b.handle, _dev(map_ids, _u32_types(), "map_ids"),
+                                      _dev(queries, _u64_types(), "queries"), queries.numel(),
+                                      _dev(vals_out, _u32_types(), "vals_out"),
+                                      _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                      missing & 0xFFFFFFFF, _stream(stream))
+    _check(rc, "fks_lookup_batch_u64")
+
+
+def fks_batch_export(b: FksBatch, index: int):
+    """(header, cells, level-two triples) of map `index` of a batch, as host arrays."""
+    import numpy as np
+    inf = fks_map_info()
+    rc = _load().fks_batch_info(b.handle, index, ctypes.byref(inf))
+    _check(rc, "fks_batch_info")
+    header = np.zeros(inf.header_bytes, np.uint8)
+    slots = np.zeros(inf.slot_bytes, np.uint8)
+    consts = np.zeros((inf.T, 3), np.uint64)
+    rc = _load().fks_batch_export(b.handle, index, header.ctypes.data if header.size else None,
+                                  slots.ctypes.data if slots.size else None, consts.ctypes.data)
+    _check(rc, "fks_batch_export")
+    return header, slots, consts, {name: getattr(inf, name) for name, _ in fks_map_info._fields_}
+
+
+def fks_batch_schedules():
+    import numpy as np
+    lib = _load()
+    cnt = lib.fks_batch_schedules(None, 0)
+    out = np.zeros(cnt, np.uint32)
+    lib.fks_batch_schedules(out.ctypes.data, cnt)
+    return [int(x) for x in out]
+
+
+def fks_batch_set_schedule(M: int, total_keys: int, schedule: int):
+    _check(_load().fks_batch_set_schedule(M, total_keys, schedule), "fks_batch_set_schedule")
+
+
+def fks_batch_destroy(b: FksBatch):
+    b.destroy()
+
+
+# ---- serving -----------------------------------------------------------------------
+
+class fks_server_stats_t(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("lookup_launches", ctypes.c_uint64), ("graph_replays", ctypes.c_uint64),
+                ("graphs_captured", ctypes.c_uint64), ("coalesced_requests", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
+                ("queries_done", ctypes.c_uint64), ("keys_built", ctypes.c_uint64),
+                ("span_ms", ctypes.c_double), ("resident_maps", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class FksServer:
+    """fks_server_*: resident maps, budgeted builds, coalesced graph-replayed lookups.
+    Keeps a reference to every tensor handed to a request until the server is waited on."""
+
+    def __init__(self, budget_bytes: int, c=None, T=None, R=None, graphs: bool = True):
+        p = _params(c, T, R)
+        out = ctypes.c_void_p()
+        _check(_load().fks_server_create(budget_bytes, ctypes.byref(p), 0 if graphs else 1, ctypes.byref(out)),
+               "fks_server_create")
+        self._h = out
+        self._keep = {}
+
+    def submit_build(self, keys, vals, seed: int):
+        rid, mid = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(_load().fks_server_submit_build(self._h, _dev(keys, _u64_types(), "keys"),
+                                               _dev(vals, _u32_types(), "vals"), keys.numel(),
+                                               seed & ((1 << 64) - 1), ctypes.byref(rid), ctypes.byref(mid)),
+               "fks_server_submit_build")
+        self._keep[rid.value] = (keys, vals)
+        return rid.value, mid.value
+
+    def submit_lookup(self, map_id: int, queries, vals_out, found_out, missing: int = 0xFFFFFFFF):
+        import torch
+        rid = ctypes.c_uint64()
+        _check(_load().fks_server_submit_lookup(self._h, map_id, _dev(queries, _u64_types(), "queries"),
+                                                queries.numel(), _dev(vals_out, _u32_types(), "vals_out"),
+                                                _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                                missing & 0xFFFFFFFF, ctypes.byref(rid)),
+               "fks_server_submit_lookup")
+        self._keep[rid.value] = (queries, vals_out, found_out)
+        return rid.value
+
+    def poll(self, rid: int):
+        done, status, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(_load().fks_server_poll(self._h, rid, ctypes.byref(done), ctypes.byref(status), ctypes.byref(lat)),
+               "fks_server_poll")
+        return bool(done.value), status.value, lat.value
+
+    def wait_all(self):
+        _check(_load().fks_server_wait_all(self._h), "fks_server_wait_all")
+        self._keep.clear()
+
+    def latencies(self, count: int):
+        import numpy as np
+        sub = np.zeros(count, np.float64)
+        done = np.zeros(count, np.float64)
+        kind = np.zeros(count, np.int32)
+        st = np.zeros(count, np.int32)
+        got = _load().fks_server_latencies(self._h, sub.ctypes.data, done.ctypes.data, kind.ctypes.data,
+                                           st.ctypes.data, count)
+        return sub[:got], done[:got], kind[:got], st[:got]
+
+    def stats(self) -> dict:
+        st = fks_server_stats_t()
+        _check(_load().fks_server_stats(self._h, ctypes.byref(st)), "fks_server_stats")
+        return {name: getattr(st, name) for name, _ in fks_server_stats_t._fields_}
+
+    def map_handle(self, map_id: int):
+        return _load().fks_server_map(self._h, map_id)
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _load().fks_server_destroy(self._h)
+        self._h = None
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -222,8 +222,8 @@ def batch_queries(keys, offsets, m: int, hit_fraction: float, seed: int):
     rng = _rng(seed)
     M = offsets.size - 1
     ids = rng.integers(0, M, size=m).astype(np.uint32)
-    hit = rng.random(m) < hit_fraction
     sizes = (offsets[1:] - offsets[:-1])
+    hit = (rng.random(m) < hit_fraction) & (sizes[ids] > 0)
     pick = (rng.random(m) * sizes[ids]).astype(np.int64)
     q = np.empty(m, np.uint64)
     q[hit] = keys[offsets[ids[hit]] + pick[hit]]
@@ -253,3 +253,40 @@ def serving_requests(count: int, rate_per_s: float, seed: int, build_fraction: f
             out.append(dict(t=float(t[i]), kind="lookup", size=size, seed=int(rng.integers(1 << 62)),
                             pick=float(rng.random())))
     return out
+
+
+# ---- counter-indexed unique keys (device or host) ----------------------------------
+# A fixed invertible mixer of 64-bit integers (odd multiplications and xor-shifts are
+# bijections mod 2^64), so distinct indices give distinct keys without a uniqueness
+# pass.  Used to make large serving workloads quickly on the GPU.  It is unrelated to
+# the hash map's own arithmetic.
+
+_MIX_A = 0xD6E8FEB86659FD93
+_MIX_B = 0xA0761D6478BD642F
+
+
+def mix_keys_np(idx):
+    x = np.asarray(idx, np.uint64)
+    with np.errstate(over="ignore"):
+        x = x * np.uint64(_MIX_A)
+        x ^= x >> np.uint64(32)
+        x = x * np.uint64(_MIX_B)
+        x ^= x >> np.uint64(29)
+    return x
+
+
+def _srl(t, s):
+    import torch
+    return (t >> s) & torch.tensor((1 << (64 - s)) - 1, dtype=torch.int64, device=t.device)
+
+
+def mix_keys_torch(idx):
+    """Same keys as mix_keys_np, computed on the tensor's device (int64 holding uint64 bits)."""
+    import torch
+    a = torch.tensor(_MIX_A - (1 << 64), dtype=torch.int64, device=idx.device)
+    b = torch.tensor(_MIX_B - (1 << 64), dtype=torch.int64, device=idx.device)
+    x = idx.to(torch.int64) * a
+    x = x ^ _srl(x, 32)
+    x = x * b
+    x = x ^ _srl(x, 29)
+    return x
