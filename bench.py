@@ -52,6 +52,10 @@ KERNEL_SRC = {
     "fks_scan_down": "paper_2508_11443_amd/csrc/build.hip",
     "fks_scan_tiles": "paper_2508_11443_amd/csrc/build.hip",
     "fks_zero_counts": "paper_2508_11443_amd/csrc/build.hip",
+    "fks_part_count": "paper_2508_11443_amd/csrc/partition.hip",
+    "fks_part_scatter": "paper_2508_11443_amd/csrc/partition.hip",
+    "fks_part_sizes": "paper_2508_11443_amd/csrc/partition.hip",
+    "fks_part_final": "paper_2508_11443_amd/csrc/partition.hip",
 }
 
 
@@ -77,6 +81,14 @@ def algorithmic_bytes(kernel, n, m, S, hit_frac, nonempty_frac):
         return G * (4 + 8)
     if kernel == "fks_zero_counts":
         return G * 4
+    if kernel == "fks_part_count":          # one counting pass: the keys
+        return n * 8
+    if kernel == "fks_part_scatter":        # one scatter pass: keys and values in and out
+        return n * (8 + 4) * 2
+    if kernel == "fks_part_sizes":          # keys in, 4-bit size words out
+        return n * 8 + G * 4
+    if kernel == "fks_part_final":          # keys and values in, cells and headers out
+        return n * (8 + 4) + S * 16 + G * 16
     return None
 
 
@@ -132,6 +144,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (known HBM bytes) for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the path shards by bucket range "
@@ -144,6 +158,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)              # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: one 1 GiB copy done")
     n = m = 1 << args.log2n
     log(f"generating workload n={n} m={m}")
     keys = workloads.unique_u64(n, DATA_SEED, dense_fraction=0.5)

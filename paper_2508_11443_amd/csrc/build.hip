@@ -23,9 +23,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <vector>
 
 #include "fks_internal.hpp"
+#include "partition.hpp"
 #include "prof.hpp"
+
+#include <cstdlib>
 
 namespace fks {
 
@@ -40,7 +44,7 @@ constexpr uint32_t kCellCap = 2048;                   // cells staged per search
 // control words of one attempt (device), read back through Readback
 struct Ctrl {
     uint64_t S;
-    uint32_t oversize, exhausted, dup, bad_input, max_t, pad;
+    uint32_t oversize, bad_input, exhausted, dup, max_t, pad;   // same layout as Readback
 };
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t v) {
@@ -52,7 +56,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t v)
 __global__ void k_zero_ctrl(Ctrl* c) {
     if (threadIdx.x == 0) {
         c->S = 0;
-        c->oversize = c->exhausted = c->dup = c->bad_input = c->max_t = c->pad = 0;
+        c->oversize = c->bad_input = c->exhausted = c->dup = c->max_t = c->pad = 0;
     }
 }
 
@@ -552,6 +556,126 @@ static int read_ctrl(Scratch& w, hipStream_t st) {
     return FKS_OK;
 }
 
+static bool legacy_build() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("FKS_BUILD_LEGACY");
+        v = (e && e[0] == '1') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+// Level-one attempts with the partitioned passes (partition.hip).
+static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uint32_t* d_vals,
+                                const fks_params& P, Ctrl* ctrl, Readback* host, uint64_t* y, hipStream_t st) {
+    const uint64_t n = M->n;
+    const uint64_t G = (n + 7) / 8;
+    const bool bytes = M->kind == 1;
+    const PartPlan plan = part_plan(n);
+    const uint32_t Q = plan.Q;
+    PartArgs a{};
+    a.n = n;
+    a.G = G;
+    a.bytes = bytes;
+    a.vals = d_vals;
+    // scratch, freed when the attempts are over
+    std::vector<void*> owned;
+    auto grab = [&](size_t bytes_) {
+        void* p = dev_alloc(bytes_, st);
+        owned.push_back(p);
+        return p;
+    };
+    auto release = [&]() {
+        for (void* p : owned) dev_free(p, st);
+        owned.clear();
+    };
+    if (plan.passes >= 2) {
+        a.k1 = (uint64_t*)grab(8 * n);
+        a.v1 = (uint32_t*)grab(4 * n);
+        if (bytes) a.a1 = (uint32_t*)grab(4 * n);
+    }
+    if (plan.passes >= 1) {
+        a.k2 = (uint64_t*)grab(8 * n);
+        a.v2 = (uint32_t*)grab(4 * n);
+        if (bytes) a.a2 = (uint32_t*)grab(4 * n);
+    }
+    a.cntA = (uint32_t*)grab(4 * 256);
+    a.offA = (uint64_t*)grab(8 * 257);
+    a.curA = (uint64_t*)grab(8 * 256);
+    a.cntQ = (uint32_t*)grab(4 * (size_t)Q);
+    a.offQ = (uint64_t*)grab(8 * ((size_t)Q + 1));
+    a.curQ = (uint64_t*)grab(8 * (size_t)Q);
+    a.sqQ = (uint32_t*)grab(4 * (size_t)Q);
+    a.cbase = (uint64_t*)grab(8 * ((size_t)Q + 1));
+    a.sizes = (uint32_t*)grab(4 * (size_t)Q * (kPartBuckets / 8));
+    a.S_dev = &ctrl->S;
+    a.oversize = &ctrl->oversize;
+    for (void* p : owned)
+        if (!p) {
+            release();
+            return FKS_ENOMEM;
+        }
+    Triple Ch[kTMax];
+    int rc = FKS_OK;
+    for (uint32_t r = 0; r < P.R; ++r) {
+        const Triple A = level1_triple(M->seed, r);
+        const uint64_t beta = level1_beta(M->seed, r);
+        a.A = A;
+        a.magic = M->magic_n;
+        a.keys = d_keys_in;
+        if (bytes) {
+            FKS_TIMED("fks_fingerprint", st,
+                      hipLaunchKernelGGL(k_fingerprint, grid_for(n, kBlock, 65536), kBlock, 0, st, M->ctx_off,
+                                         M->ctx_bytes, n, beta, y));
+            a.keys = y;
+        }
+        hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
+        PartOut o;
+        if ((rc = part_prepare(a, st, o))) break;
+        FKS_HIP(hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st));
+        FKS_HIP(hipStreamSynchronize(st));
+        if (host->oversize) continue;
+        const uint64_t S = host->S;
+        if (S > (uint64_t)P.c * n) continue;
+        for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
+        FKS_HIP(hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st));
+        Cell* slots = (Cell*)dev_alloc(16 * (S ? S : 1), st);
+        if (!slots) {
+            rc = FKS_ENOMEM;
+            break;
+        }
+        rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off, M->ctx_bytes, st);
+        if (rc == FKS_OK) {
+            hipError_t e = hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
+        if (rc) {
+            dev_free(slots, st);
+            break;
+        }
+        if (host->exhausted) {
+            dev_free(slots, st);
+            if (host->dup) {
+                rc = FKS_EDUPKEY;
+                break;
+            }
+            continue;
+        }
+        M->slots = slots;
+        M->S = S;
+        M->r = r;
+        M->A = A;
+        M->beta = beta;
+        M->max_t = host->max_t;
+        M->device_bytes += 16 * S;
+        release();
+        return FKS_OK;
+    }
+    release();
+    return rc ? rc : FKS_EBUILD;
+}
+
 // keys: device u64 keys (or fingerprints); vals; aux_is_index for string maps
 static int build_common(fks_map* M, const uint64_t* d_keys_in, const uint32_t* d_vals,
                         const int64_t* d_off, const uint8_t* d_bytes, uint64_t nbytes,
@@ -566,15 +690,18 @@ static int build_common(fks_map* M, const uint64_t* d_keys_in, const uint32_t* d
         free_scratch(w, st);
         return code;
     };
-    w.sizes = (uint32_t*)dev_alloc(4 * G, st);
-    w.rank = (uint8_t*)dev_alloc(n, st);
-    w.gscan = (uint2*)dev_alloc(8 * G, st);
-    w.tiles = (uint64_t*)dev_alloc(16 * ntiles, st);
-    w.grouped = (Cell*)dev_alloc(16 * n, st);
+    const bool legacy = legacy_build();
+    if (legacy) {
+        w.sizes = (uint32_t*)dev_alloc(4 * G, st);
+        w.rank = (uint8_t*)dev_alloc(n, st);
+        w.gscan = (uint2*)dev_alloc(8 * G, st);
+        w.tiles = (uint64_t*)dev_alloc(16 * ntiles, st);
+        w.grouped = (Cell*)dev_alloc(16 * n, st);
+        if (!w.sizes || !w.rank || !w.gscan || !w.tiles || !w.grouped) return fail(FKS_ENOMEM);
+    }
     w.ctrl = (Ctrl*)dev_alloc(sizeof(Ctrl), st);
     if (bytes) w.y = (uint64_t*)dev_alloc(8 * n, st);
-    if (!w.sizes || !w.rank || !w.gscan || !w.tiles || !w.grouped || !w.ctrl || (bytes && !w.y))
-        return fail(FKS_ENOMEM);
+    if (!w.ctrl || (bytes && !w.y)) return fail(FKS_ENOMEM);
     w.host = pinned_readback();
     if (!w.host) return fail(FKS_ENOMEM);
     M->header = (Group*)dev_alloc(16 * G, st);
@@ -600,6 +727,11 @@ static int build_common(fks_map* M, const uint64_t* d_keys_in, const uint32_t* d
     Triple Ch[kTMax];
     const uint64_t magic = fastmod_magic((uint32_t)n);
     M->magic_n = magic;
+    if (!legacy_build()) {
+        rc = attempts_partitioned(M, d_keys_in, d_vals, P, w.ctrl, w.host, w.y, st);
+        free_scratch(w, st);
+        return rc;
+    }
     for (uint32_t r = 0; r < P.R; ++r) {
         const Triple A = level1_triple(M->seed, r);
         const uint64_t beta = level1_beta(M->seed, r);

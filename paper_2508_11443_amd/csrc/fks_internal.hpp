@@ -171,9 +171,9 @@ void dev_free(void* p, hipStream_t s);
 struct Readback {
     uint64_t S;          // sum of squared sizes of the attempt
     uint32_t oversize;   // some bucket holds more than 15 keys
+    uint32_t bad_input;  // string offsets not monotone / out of range
     uint32_t exhausted;  // some bucket ran out of level-two trials
     uint32_t dup;        // an exhausted bucket holds two equal keys
-    uint32_t bad_input;  // string offsets not monotone / out of range
     uint32_t max_t;
     uint32_t pad;
 };

@@ -1,0 +1,628 @@
+// Partitioned construction: the level-one attempt as a few streaming passes.
+//
+// Buckets are cut into partitions of 1024 consecutive buckets (q = j >> 10).
+// Keys are moved into partition order by one or two coalescing scatter passes
+// (at most 256 bins per pass, so every 4096-key tile writes runs of about 16
+// records per bin), then every partition is finished by one workgroup that
+// holds its ~1024 keys in LDS: histogram with LDS atomics (the ranks come with
+// it), scan of the 128 group statistics, grouping, the per-bucket level-two
+// search of make_2, and the coalesced write of the partition's contiguous cells
+// and group headers.  Only the partition totals of squared sizes (the offsets
+// of Section 2.2, at partition granularity) cross partitions: one small pass
+// computes them, one single-block scan turns them into cell bases and the
+// table size S.  Device-scope atomics are used only on a few hundred to a few
+// tens of thousands of counters, once per tile and bin; every per-key access
+// is a coalesced stream or LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fks_internal.hpp"
+#include "partition.hpp"
+#include "prof.hpp"
+
+namespace fks {
+
+constexpr uint32_t kPB = 256;                 // threads per block, partition passes
+constexpr uint32_t kPItems = 16;              // keys per thread per tile
+constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
+constexpr uint32_t kBins = 256;               // bins per scatter pass
+constexpr uint32_t kFinalKeyCap = 1536;       // keys of one partition held in LDS (mean 1024)
+constexpr uint32_t kFinalCellCap = 4096;      // cells of one partition staged in LDS (mean ~2048)
+constexpr uint32_t kGroupsPerPart = kPartBuckets / 8;
+
+__global__ void k_zero_words(uint32_t* __restrict__ p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_set_range(uint64_t* off, uint64_t n) {
+    if (threadIdx.x == 0) {
+        off[0] = 0;
+        off[1] = n;
+    }
+}
+
+__device__ __forceinline__ uint32_t bucket_of(const Triple& A, uint64_t magic, uint32_t n, uint64_t x) {
+    return fastmod(mshash(A, x), magic, n);
+}
+
+// Tiles of the key range [lo, hi): the whole input (ranges == nullptr) or the
+// partition blockIdx.y of a previous pass (ranges[p] .. ranges[p+1]).
+__device__ __forceinline__ void tile_range(const uint64_t* ranges, uint64_t n, uint64_t& lo, uint64_t& hi,
+                                           uint32_t& prefix, uint32_t bitsB) {
+    if (ranges) {
+        lo = ranges[blockIdx.y];
+        hi = ranges[blockIdx.y + 1];
+        prefix = blockIdx.y << bitsB;
+    } else {
+        lo = 0;
+        hi = n;
+        prefix = 0;
+    }
+}
+
+// count keys per bin: bin = ((j >> 10) >> shift) & mask, counter index prefix + bin
+__global__ __launch_bounds__(kPB) void k_pcount(const uint64_t* __restrict__ keys, uint64_t n, Triple A,
+                                                  uint64_t magic, const uint64_t* __restrict__ ranges,
+                                                  uint32_t shift, uint32_t mask, uint32_t bitsB,
+                                                  uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t bins[kBins];
+    uint64_t lo, hi;
+    uint32_t prefix;
+    tile_range(ranges, n, lo, hi, prefix, bitsB);
+    for (uint32_t b = threadIdx.x; b < kBins; b += kPB) bins[b] = 0;
+    __syncthreads();
+    for (uint64_t ts = lo + (uint64_t)blockIdx.x * kPTile; ts < hi; ts += (uint64_t)gridDim.x * kPTile) {
+        uint64_t x[kPItems];
+#pragma unroll
+        for (uint32_t k = 0; k < kPItems; ++k) {
+            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
+            x[k] = i < hi ? keys[i] : 0;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kPItems; ++k) {
+            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
+            if (i < hi) {
+                const uint32_t q = bucket_of(A, magic, (uint32_t)n, x[k]) >> kPartBits;
+                atomicAdd(&bins[(q >> shift) & mask], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kBins; b += kPB)
+        if (bins[b]) atomicAdd(&cnt[prefix + b], bins[b]);
+}
+
+// scatter keys (and values, and string indices) to cursor[prefix + bin] runs
+template <bool AUX>
+__global__ __launch_bounds__(kPB) void k_pscatter(const uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ aux, uint64_t n, Triple A,
+                                                    uint64_t magic, const uint64_t* __restrict__ ranges,
+                                                    uint32_t shift, uint32_t mask, uint32_t bitsB,
+                                                    uint64_t* __restrict__ cursor, uint64_t* __restrict__ keys_out,
+                                                    uint32_t* __restrict__ vals_out, uint32_t* __restrict__ aux_out) {
+    __shared__ uint32_t bins[kBins];
+    __shared__ uint64_t base[kBins];
+    uint64_t lo, hi;
+    uint32_t prefix;
+    tile_range(ranges, n, lo, hi, prefix, bitsB);
+    for (uint64_t ts = lo + (uint64_t)blockIdx.x * kPTile; ts < hi; ts += (uint64_t)gridDim.x * kPTile) {
+        for (uint32_t b = threadIdx.x; b < kBins; b += kPB) bins[b] = 0;
+        __syncthreads();
+        uint64_t x[kPItems];
+        uint32_t bin[kPItems], rank[kPItems];
+#pragma unroll
+        for (uint32_t k = 0; k < kPItems; ++k) {
+            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
+            x[k] = i < hi ? keys[i] : 0;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kPItems; ++k) {
+            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
+            if (i < hi) {
+                const uint32_t q = bucket_of(A, magic, (uint32_t)n, x[k]) >> kPartBits;
+                bin[k] = (q >> shift) & mask;
+                rank[k] = atomicAdd(&bins[bin[k]], 1u);
+            }
+        }
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < kBins; b += kPB)
+            base[b] = bins[b] ? atomicAdd((unsigned long long*)&cursor[prefix + b], (unsigned long long)bins[b]) : 0;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < kPItems; ++k) {
+            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
+            if (i < hi) {
+                const uint64_t pos = base[bin[k]] + rank[k];
+                keys_out[pos] = x[k];
+                vals_out[pos] = vals[i];
+                if (AUX) aux_out[pos] = aux ? aux[i] : (uint32_t)i;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// single block: exclusive prefix of cnt[0..N) into off (u64), copy into cursor,
+// off[N] = total; the total also into *total when given
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ cnt, uint32_t N,
+                                                        uint64_t* __restrict__ off, uint64_t* __restrict__ cursor,
+                                                        uint64_t* __restrict__ total) {
+    __shared__ uint64_t part[1024];
+    const uint32_t per = (N + 1023) / 1024;
+    const uint32_t a = threadIdx.x * per, b = min(N, a + per);
+    uint64_t s = 0;
+    for (uint32_t i = a; i < b; ++i) s += cnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        const uint64_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[threadIdx.x] - s;
+    for (uint32_t i = a; i < b; ++i) {
+        off[i] = run;
+        if (cursor) cursor[i] = run;
+        run += cnt[i];
+    }
+    if (threadIdx.x == 1023) {
+        off[N] = part[1023];
+        if (total) *total = part[1023];
+    }
+}
+
+// per partition: 4-bit bucket sizes (written to the global size words) and the
+// partition's sum of squared sizes
+__global__ __launch_bounds__(kPB) void k_psizes(const uint64_t* __restrict__ keys, uint64_t n, Triple A,
+                                                  uint64_t magic, const uint64_t* __restrict__ offQ,
+                                                  uint32_t* __restrict__ sizes, uint64_t G,
+                                                  uint32_t* __restrict__ sq_out, uint32_t* __restrict__ oversize) {
+    __shared__ uint32_t words[kGroupsPerPart];
+    __shared__ uint32_t red[kPB / 64];
+    const uint32_t q = blockIdx.x;
+    for (uint32_t g = threadIdx.x; g < kGroupsPerPart; g += kPB) words[g] = 0;
+    __syncthreads();
+    const uint64_t lo = offQ[q], hi = offQ[q + 1];
+    bool over = false;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kPB) {
+        const uint32_t lb = bucket_of(A, magic, (uint32_t)n, keys[i]) & (kPartBuckets - 1);
+        const uint32_t sh = 4 * (lb & 7u);
+        const uint32_t old = atomicAdd(&words[lb >> 3], 1u << sh);
+        over |= ((old >> sh) & 15u) == 15u;
+    }
+    if (over) atomicOr(oversize, 1u);
+    __syncthreads();
+    uint32_t sq = 0;
+    for (uint32_t g = threadIdx.x; g < kGroupsPerPart; g += kPB) {
+        const uint32_t w = words[g];
+        const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
+        if (gg < G) sizes[gg] = w;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t s = nib(w, k);
+            sq += s * s;
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) sq += __shfl_xor(sq, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < kPB / 64; ++w) t += red[w];
+        sq_out[q] = t;
+    }
+}
+
+__device__ __forceinline__ bool test_set4(uint64_t& m0, uint64_t& m1, uint64_t& m2, uint64_t& m3, uint32_t h) {
+    const uint64_t bit = 1ull << (h & 63u);
+    const uint32_t w = h >> 6;
+    const uint64_t cur = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
+    if (cur & bit) return true;
+    if (w == 0) m0 |= bit;
+    else if (w == 1) m1 |= bit;
+    else if (w == 2) m2 |= bit;
+    else m3 |= bit;
+    return false;
+}
+
+template <typename KeyAt>
+__device__ __forceinline__ uint32_t min_trial(const Triple* C, uint32_t T, uint32_t s, KeyAt key_at) {
+    const uint32_t s2 = s * s;
+    for (uint32_t t = 0; t < T; ++t) {
+        const Triple c = C[t];
+        uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+        bool collide = false;
+        for (uint32_t i = 0; i < s && !collide; ++i) collide = test_set4(m0, m1, m2, m3, mshash(c, key_at(i)) % s2);
+        if (!collide) return t;
+    }
+    return T;
+}
+
+__device__ __forceinline__ bool same_string(const int64_t* off, const uint8_t* bytes, uint32_t a, uint32_t b) {
+    const int64_t la = off[a + 1] - off[a], lb = off[b + 1] - off[b];
+    if (la != lb) return false;
+    const uint8_t* pa = bytes + off[a];
+    const uint8_t* pb = bytes + off[b];
+    for (int64_t i = 0; i < la; ++i)
+        if (pa[i] != pb[i]) return false;
+    return true;
+}
+
+template <bool BYTES>
+struct FinalLds {
+    uint64_t key[kFinalKeyCap];
+    uint32_t val[kFinalKeyCap];
+    uint32_t aux[BYTES ? kFinalKeyCap : 1];
+    uint16_t lb[kFinalKeyCap];
+    uint16_t perm[kFinalKeyCap];
+    uint8_t rank[kFinalKeyCap];
+    uint16_t smap[kFinalCellCap];
+    uint32_t words[kGroupsPerPart];
+    uint32_t cnt2[kGroupsPerPart];
+    uint32_t gks[kGroupsPerPart];
+    uint32_t gbase[kGroupsPerPart];
+    uint8_t tb[kPartBuckets];
+    uint32_t wsum[2][kPB / 64];
+    uint32_t flags[3];   // exhausted, dup, max_t
+};
+
+template <bool BYTES>
+__global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                  const uint32_t* __restrict__ aux, int aux_is_pos, uint64_t n,
+                                                  Triple A, uint64_t magic, const uint64_t* __restrict__ offQ,
+                                                  const uint64_t* __restrict__ cbase, const uint32_t* __restrict__ sizes,
+                                                  uint64_t G, const Triple* __restrict__ Cg, uint32_t T,
+                                                  Group* __restrict__ header, Cell* __restrict__ slots,
+                                                  uint32_t* __restrict__ ctrl_flags, const int64_t* __restrict__ ctx_off,
+                                                  const uint8_t* __restrict__ ctx_bytes) {
+    __shared__ FinalLds<BYTES> L;
+    extern __shared__ Triple Cdyn[];   // the T level-two triples
+    Triple* const LC = Cdyn;
+    const uint32_t q = blockIdx.x, tid = threadIdx.x;
+    const uint64_t k0 = offQ[q], k1 = offQ[q + 1];
+    const uint32_t nq = (uint32_t)(k1 - k0);
+    const uint64_t c0 = cbase[q];
+    const uint32_t Sq = (uint32_t)(cbase[q + 1] - c0);
+    for (uint32_t t = tid; t < T; t += kPB) LC[t] = Cg[t];
+    for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) {
+        const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
+        L.words[g] = gg < G ? sizes[gg] : 0u;
+    }
+    if (tid < 3) L.flags[tid] = 0;
+    __syncthreads();
+    // group statistics: where each group's keys and cells start inside the partition
+    {
+        uint32_t c = 0, s2 = 0;
+        if (tid < kGroupsPerPart) {
+            const uint32_t w = L.words[tid];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t s = nib(w, k);
+                c += s;
+                s2 += s * s;
+            }
+        }
+        uint32_t ic = c, is = s2;
+        const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t uc = __shfl_up(ic, d, 64), us = __shfl_up(is, d, 64);
+            if (lane >= d) {
+                ic += uc;
+                is += us;
+            }
+        }
+        if (lane == 63) {
+            L.wsum[0][wv] = ic;
+            L.wsum[1][wv] = is;
+        }
+        __syncthreads();
+        uint32_t pc = 0, ps = 0;
+        for (int w = 0; w < wv; ++w) {
+            pc += L.wsum[0][w];
+            ps += L.wsum[1][w];
+        }
+        if (tid < kGroupsPerPart) {
+            L.gks[tid] = pc + ic - c;
+            L.gbase[tid] = ps + is - s2;
+        }
+    }
+    const bool fast = nq <= kFinalKeyCap && Sq <= kFinalCellCap;
+    if (fast) {
+        // stage the partition's keys; ranks come from a second LDS histogram
+        for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < nq; i += kPB) {
+            const uint64_t x = keys[k0 + i];
+            L.key[i] = x;
+            L.val[i] = vals[k0 + i];
+            if (BYTES) L.aux[i] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
+            const uint32_t lb = bucket_of(A, magic, (uint32_t)n, x) & (kPartBuckets - 1);
+            L.lb[i] = (uint16_t)lb;
+            const uint32_t sh = 4 * (lb & 7u);
+            L.rank[i] = (uint8_t)((atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u);
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < nq; i += kPB) {
+            const uint32_t lb = L.lb[i], g = lb >> 3;
+            L.perm[L.gks[g] + prefix_cnt(L.words[g], lb & 7u) + L.rank[i]] = (uint16_t)i;
+        }
+        __syncthreads();
+        for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
+            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
+            const uint32_t s = nib(w, kk);
+            const uint32_t kst = L.gks[g] + prefix_cnt(w, kk);
+            const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
+            uint32_t t = 0;
+            bool exhausted = false;
+            if (s >= 2) {
+                t = min_trial(LC, T, s, [&](uint32_t i) { return L.key[L.perm[kst + i]]; });
+                exhausted = t == T;
+            }
+            const uint32_t s2 = s * s;
+            if (s >= 1) {
+                if (!exhausted) {
+                    for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = 0xFFFFu;
+                    const Triple c = LC[t];
+                    for (uint32_t i = 0; i < s; ++i) {
+                        const uint16_t who = L.perm[kst + i];
+                        L.smap[off + mshash(c, L.key[who]) % s2] = who;
+                    }
+                    uint16_t first = 0;
+                    for (uint32_t p = 0; p < s2; ++p)
+                        if (L.smap[off + p] != 0xFFFFu) {
+                            first = L.smap[off + p];
+                            break;
+                        }
+                    for (uint32_t p = 0; p < s2; ++p)
+                        if (L.smap[off + p] == 0xFFFFu) L.smap[off + p] = first;
+                } else {
+                    for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = L.perm[kst];
+                    bool dup = false;
+                    for (uint32_t a = 0; a < s; ++a)
+                        for (uint32_t b2 = a + 1; b2 < s; ++b2) {
+                            const uint16_t ia = L.perm[kst + a], ib = L.perm[kst + b2];
+                            if (BYTES) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
+                            else dup |= L.key[ia] == L.key[ib];
+                        }
+                    atomicOr(&L.flags[0], 1u);
+                    if (dup) atomicOr(&L.flags[1], 1u);
+                }
+            }
+            if (exhausted) t = 0;
+            if (t) atomicMax(&L.flags[2], t);
+            L.tb[b] = (uint8_t)t;
+        }
+        __syncthreads();
+        for (uint32_t p = tid; p < Sq; p += kPB) {
+            const uint16_t i = L.smap[p];
+            Cell c;
+            c.key = L.key[i];
+            c.val = L.val[i];
+            c.aux = BYTES ? L.aux[i] : 0u;
+            slots[c0 + p] = c;
+        }
+    } else {
+        // rare: the partition does not fit the LDS staging; every bucket gathers its
+        // own keys from HBM (a scan of the partition), searches and writes its cells
+        __syncthreads();
+        for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
+            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
+            const uint32_t s = nib(w, kk);
+            const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
+            uint64_t mine[kSMax];
+            uint32_t pos[kSMax];
+            uint32_t got = 0;
+            if (s) {
+                for (uint32_t i = 0; i < nq && got < s; ++i) {
+                    const uint64_t x = keys[k0 + i];
+                    if ((bucket_of(A, magic, (uint32_t)n, x) & (kPartBuckets - 1)) == b) {
+                        mine[got] = x;
+                        pos[got] = i;
+                        ++got;
+                    }
+                }
+            }
+            uint32_t t = 0;
+            bool exhausted = false;
+            if (s >= 2) {
+                t = min_trial(LC, T, s, [&](uint32_t i) { return mine[i]; });
+                exhausted = t == T;
+            }
+            const uint32_t s2 = s * s;
+            if (s >= 1 && !exhausted) {
+                const Triple c = LC[t];
+                uint32_t first_p = s2, first_i = 0;
+                for (uint32_t i = 0; i < s; ++i) {
+                    const uint32_t h = mshash(c, mine[i]) % s2;
+                    if (h < first_p) {
+                        first_p = h;
+                        first_i = i;
+                    }
+                }
+                for (uint32_t p = 0; p < s2; ++p) {
+                    uint32_t who = first_i;
+                    for (uint32_t i = 0; i < s; ++i)
+                        if (mshash(c, mine[i]) % s2 == p) who = i;
+                    Cell cl;
+                    cl.key = mine[who];
+                    cl.val = vals[k0 + pos[who]];
+                    cl.aux = BYTES ? (aux_is_pos ? (uint32_t)(k0 + pos[who]) : aux[k0 + pos[who]]) : 0u;
+                    slots[c0 + off + p] = cl;
+                }
+            }
+            if (exhausted) {
+                bool dup = false;
+                for (uint32_t a = 0; a < s; ++a)
+                    for (uint32_t b2 = a + 1; b2 < s; ++b2) {
+                        if (BYTES) {
+                            const uint32_t xa = aux_is_pos ? (uint32_t)(k0 + pos[a]) : aux[k0 + pos[a]];
+                            const uint32_t xb = aux_is_pos ? (uint32_t)(k0 + pos[b2]) : aux[k0 + pos[b2]];
+                            dup |= same_string(ctx_off, ctx_bytes, xa, xb);
+                        } else {
+                            dup |= mine[a] == mine[b2];
+                        }
+                    }
+                atomicOr(&L.flags[0], 1u);
+                if (dup) atomicOr(&L.flags[1], 1u);
+                t = 0;
+            }
+            if (t) atomicMax(&L.flags[2], t);
+            L.tb[b] = (uint8_t)t;
+        }
+        __syncthreads();
+    }
+    for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) {
+        const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
+        if (gg < G) {
+            Group h;
+            h.base = (uint32_t)(c0 + L.gbase[g]);
+            h.sizes = L.words[g];
+            h.t_lo = (uint32_t)L.tb[8 * g] | ((uint32_t)L.tb[8 * g + 1] << 8) | ((uint32_t)L.tb[8 * g + 2] << 16) |
+                     ((uint32_t)L.tb[8 * g + 3] << 24);
+            h.t_hi = (uint32_t)L.tb[8 * g + 4] | ((uint32_t)L.tb[8 * g + 5] << 8) |
+                     ((uint32_t)L.tb[8 * g + 6] << 16) | ((uint32_t)L.tb[8 * g + 7] << 24);
+            header[gg] = h;
+        }
+    }
+    if (tid == 0) {
+        if (L.flags[0]) atomicOr(&ctrl_flags[0], 1u);
+        if (L.flags[1]) atomicOr(&ctrl_flags[1], 1u);
+        if (L.flags[2]) atomicMax(&ctrl_flags[2], L.flags[2]);
+    }
+}
+
+// ---- host planning and launches ------------------------------------------------------
+
+PartPlan part_plan(uint64_t n) {
+    PartPlan P{};
+    P.Q = (uint32_t)((n + kPartBuckets - 1) / kPartBuckets);
+    uint32_t bits = 0;
+    while ((1ull << bits) < P.Q) ++bits;
+    P.bits_q = bits;
+    if (P.Q <= 1) {
+        P.passes = 0;
+    } else if (bits <= 8) {
+        P.passes = 1;
+        P.shiftA = 0;
+        P.binsA = P.Q;
+        P.bitsB = 0;
+    } else {
+        P.passes = 2;
+        P.shiftA = bits - 8;
+        P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
+        P.bitsB = P.shiftA;
+    }
+    return P;
+}
+
+static unsigned tiles_of(uint64_t n) {
+    uint64_t t = (n + kPTile - 1) / kPTile;
+    return (unsigned)(t ? t : 1);
+}
+
+// Runs passes for attempt A; on return (stream-ordered) offQ, the partitioned
+// records (pointed to by *rk/*rv/*ra), per-partition squares and their scan
+// (cbase, total S in *S_dev) and the sizes words are in place.
+int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
+    const PartPlan P = part_plan(a.n);
+    const uint64_t n = a.n;
+    const bool bytes = a.bytes;
+    o.plan = P;
+    o.keys = a.keys;
+    o.vals = a.vals;
+    o.aux = nullptr;
+    o.aux_is_pos = 1;
+    hipError_t e = hipSuccess;
+    // fill counters with a kernel (no memset nodes in streams that might be captured)
+    auto zero = [&](void* p, size_t words) {
+        hipLaunchKernelGGL(k_zero_words, (unsigned)((words + 255) / 256 > 4096 ? 4096 : (words + 255) / 256 + 1),
+                           256, 0, st, (uint32_t*)p, (uint64_t)words);
+    };
+    if (P.passes == 0) {
+        // one partition: offQ = {0, n}
+        hipLaunchKernelGGL(k_set_range, 1, 64, 0, st, a.offQ, n);
+    } else if (P.passes == 1) {
+        zero(a.cntQ, P.Q);
+        FKS_TIMED("fks_part_count", st,
+                  hipLaunchKernelGGL(k_pcount, std::min(tiles_of(n), 2048u), kPB, 0, st, a.keys, n, a.A, a.magic,
+                                     nullptr, 0u, 255u, 0u, a.cntQ));
+        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.cntQ, P.Q, a.offQ, a.curQ, nullptr);
+        if (bytes)
+            FKS_TIMED("fks_part_scatter", st,
+                      hipLaunchKernelGGL(k_pscatter<true>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n, a.A,
+                                         a.magic, nullptr, 0u, 255u, 0u, a.curQ, a.k2, a.v2, a.a2));
+        else
+            FKS_TIMED("fks_part_scatter", st,
+                      hipLaunchKernelGGL(k_pscatter<false>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n,
+                                         a.A, a.magic, nullptr, 0u, 255u, 0u, a.curQ, a.k2, a.v2, a.a2));
+        o.keys = a.k2;
+        o.vals = a.v2;
+        o.aux = a.a2;
+        o.aux_is_pos = bytes ? 0 : 1;
+    } else {
+        zero(a.cntA, 256);
+        zero(a.cntQ, P.Q);
+        FKS_TIMED("fks_part_count", st,
+                  hipLaunchKernelGGL(k_pcount, std::min(tiles_of(n), 2048u), kPB, 0, st, a.keys, n, a.A, a.magic,
+                                     nullptr, P.shiftA, 255u, 0u, a.cntA));
+        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.cntA, P.binsA, a.offA, a.curA, nullptr);
+        if (bytes)
+            FKS_TIMED("fks_part_scatter", st,
+                      hipLaunchKernelGGL(k_pscatter<true>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n, a.A,
+                                         a.magic, nullptr, P.shiftA, 255u, 0u, a.curA, a.k1, a.v1, a.a1));
+        else
+            FKS_TIMED("fks_part_scatter", st,
+                      hipLaunchKernelGGL(k_pscatter<false>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n,
+                                         a.A, a.magic, nullptr, P.shiftA, 255u, 0u, a.curA, a.k1, a.v1, a.a1));
+        // second level, inside every first-level partition
+        const uint32_t maskB = (1u << P.bitsB) - 1;
+        const unsigned per = std::max(1u, std::min(64u, tiles_of(n / std::max(1u, P.binsA)) + 1));
+        dim3 grid2(per, P.binsA);
+        FKS_TIMED("fks_part_count", st,
+                  hipLaunchKernelGGL(k_pcount, grid2, kPB, 0, st, a.k1, n, a.A, a.magic, a.offA, 0u, maskB, P.bitsB,
+                                     a.cntQ));
+        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.cntQ, P.Q, a.offQ, a.curQ, nullptr);
+        if (bytes)
+            FKS_TIMED("fks_part_scatter", st,
+                      hipLaunchKernelGGL(k_pscatter<true>, grid2, kPB, 0, st, a.k1, a.v1, a.a1, n, a.A, a.magic,
+                                         a.offA, 0u, maskB, P.bitsB, a.curQ, a.k2, a.v2, a.a2));
+        else
+            FKS_TIMED("fks_part_scatter", st,
+                      hipLaunchKernelGGL(k_pscatter<false>, grid2, kPB, 0, st, a.k1, a.v1, nullptr, n, a.A, a.magic,
+                                         a.offA, 0u, maskB, P.bitsB, a.curQ, a.k2, a.v2, a.a2));
+        o.keys = a.k2;
+        o.vals = a.v2;
+        o.aux = a.a2;
+        o.aux_is_pos = bytes ? 0 : 1;
+    }
+    FKS_TIMED("fks_part_sizes", st,
+              hipLaunchKernelGGL(k_psizes, P.Q, kPB, 0, st, o.keys, n, a.A, a.magic, a.offQ, a.sizes, a.G, a.sqQ,
+                                 a.oversize));
+    hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.sqQ, P.Q, a.cbase, nullptr, a.S_dev);
+    e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
+int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
+                uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, hipStream_t st) {
+    if (a.bytes)
+        FKS_TIMED("fks_part_final", st,
+                  hipLaunchKernelGGL(k_pfinal<true>, o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals, o.aux, o.aux_is_pos, a.n,
+                                     a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header, slots, flags,
+                                     ctx_off, ctx_bytes));
+    else
+        FKS_TIMED("fks_part_final", st,
+                  hipLaunchKernelGGL(k_pfinal<false>, o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals, nullptr, 1, a.n, a.A,
+                                     a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header, slots, flags, nullptr,
+                                     nullptr));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
+}  // namespace fks

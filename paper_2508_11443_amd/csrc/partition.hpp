@@ -1,0 +1,59 @@
+// Partitioned level-one attempt (partition.hip): plan, buffers, entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fks_internal.hpp"
+
+namespace fks {
+
+constexpr uint32_t kPartBits = 10;                   // 1024 buckets per partition
+constexpr uint32_t kPartBuckets = 1u << kPartBits;
+
+struct PartPlan {
+    uint32_t Q;        // partitions
+    uint32_t bits_q;   // ceil(log2 Q)
+    uint32_t passes;   // scatter passes: 0, 1 or 2
+    uint32_t shiftA;   // first-level bin = q >> shiftA
+    uint32_t binsA;    // first-level bins
+    uint32_t bitsB;    // second-level bin = q & (2^bitsB - 1)
+};
+
+// Inputs, scratch and outputs of one attempt (device pointers).
+struct PartArgs {
+    uint64_t n, G;
+    bool bytes;
+    Triple A;
+    uint64_t magic;
+    const uint64_t* keys;       // the integers the construction hashes
+    const uint32_t* vals;
+    // scratch
+    uint64_t *k1, *k2;          // partitioned keys after pass 1 / pass 2
+    uint32_t *v1, *v2;          // values
+    uint32_t *a1, *a2;          // string indices (string maps)
+    uint32_t* cntA;             // 256 first-level counters
+    uint64_t *offA, *curA;      // 257 offsets, 256 cursors
+    uint32_t* cntQ;             // Q partition counters
+    uint64_t *offQ, *curQ;      // Q+1 offsets, Q cursors
+    uint32_t* sqQ;              // Q sums of squared sizes
+    uint64_t* cbase;            // Q+1 cell bases
+    uint32_t* sizes;            // G size words (the headers' second word)
+    uint64_t* S_dev;            // total cells
+    uint32_t* oversize;         // a bucket above 15 keys
+};
+
+struct PartOut {
+    PartPlan plan;
+    const uint64_t* keys;       // records in partition order
+    const uint32_t* vals;
+    const uint32_t* aux;
+    int aux_is_pos;
+};
+
+PartPlan part_plan(uint64_t n);
+int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o);
+int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
+                uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, hipStream_t st);
+
+}  // namespace fks
