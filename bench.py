@@ -136,6 +136,147 @@ def cpu_baseline(keys, vals, q, n, m, budget_s):
             "build_mkeys_per_s": round(ns / tb / 1e6, 3), "lookup_mq_per_s": round(ns / tl / 1e6, 3)}
 
 
+def _median_ms(fn, reps, stream):
+    import torch
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+        if hasattr(r, "destroy"):
+            r.destroy()
+    return float(np.median(out))
+
+
+def extra_strings(dev, reps=5):
+    """Config 3: 2^22 unique lowercase strings (4..64 bytes), 2^22 needles at 50% hits."""
+    import torch
+    from paper_2508_11443_amd import fks, workloads
+    n = 1 << 22
+    off, data = workloads.random_strings(n, 303)
+    qo, qd, qf, _ = workloads.string_queries(off, data, n, 0.5, 304)
+    d_off = torch.from_numpy(off).to(dev)
+    d_data = torch.from_numpy(data).to(dev)
+    d_vals = torch.arange(n, dtype=torch.int32, device=dev)
+    d_qo = torch.from_numpy(qo).to(dev)
+    d_qd = torch.from_numpy(qd).to(dev)
+    v = torch.empty(n, dtype=torch.int32, device=dev)
+    f = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream()
+    fks.fks_build_bytes(d_off, d_data, d_vals, 7, stream=st).destroy()
+    tb = _median_ms(lambda: fks.fks_build_bytes(d_off, d_data, d_vals, 7, stream=st), reps, st)
+    m = fks.fks_build_bytes(d_off, d_data, d_vals, 7, stream=st)
+    tl = _median_ms(lambda: fks.fks_lookup_bytes(m, d_qo, d_qd, v, f, stream=st), reps, st)
+    ok = bool(torch.equal(f.cpu(), torch.from_numpy(qf)))
+    m.destroy()
+    return {"config": "2^22 unique strings, lengths 4..64, lowercase; 2^22 needles, 50% hits",
+            "build_ms": round(tb, 4), "lookup_ms": round(tl, 4),
+            "build_mkeys_per_s": round(n / tb / 1e3, 1), "lookup_mq_per_s": round(n / tl / 1e3, 1),
+            "context_bytes": int(data.size), "answers_checked": ok}
+
+
+def extra_batch(dev, reps=5):
+    """Config 4: 4096 maps (log-uniform 16..2^16 keys) in one persistent launch, then 2^24
+    needles (75% hits) over them; against the same maps built and queried one map per call."""
+    import torch
+    from paper_2508_11443_amd import autotune, fks, workloads
+    M = 4096
+    keys, vals, off = workloads.batch_u64(M, 404)
+    ids, q, exp_f, exp_v = workloads.batch_queries(keys, off, 1 << 24, 0.75, 405)
+    d_keys = torch.from_numpy(keys.view(np.int64)).to(dev)
+    d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
+    st = torch.cuda.current_stream()
+    tune = autotune.tune_batch(d_keys, d_vals, off, batch_seed=9, reps=3)
+    tb = _median_ms(lambda: fks.fks_build_batch_u64(d_keys, d_vals, off, 9, stream=st), reps, st)
+    b = fks.fks_build_batch_u64(d_keys, d_vals, off, 9, stream=st)
+    d_ids = torch.from_numpy(ids.view(np.int32)).to(dev)
+    d_q = torch.from_numpy(q.view(np.int64)).to(dev)
+    v = torch.empty(q.size, dtype=torch.int32, device=dev)
+    f = torch.empty(q.size, dtype=torch.uint8, device=dev)
+    tl = _median_ms(lambda: fks.fks_lookup_batch_u64(b, d_ids, d_q, v, f, stream=st), reps, st)
+    ok = bool(torch.equal(f.cpu(), torch.from_numpy(exp_f)))
+    hit = torch.from_numpy(exp_f.astype(bool))
+    ok = ok and bool(torch.equal(v.cpu()[hit], torch.from_numpy(exp_v.view(np.int32))[hit]))
+    b.destroy()
+    # the plain form: one build call per map, then one lookup call per map
+    from paper_2508_11443_amd import fks as F
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    maps = []
+    for m_ in range(M):
+        lo, hi = int(off[m_]), int(off[m_ + 1])
+        maps.append(F.fks_build_u64(d_keys[lo:hi], d_vals[lo:hi], m_ + 1, stream=st))
+    torch.cuda.synchronize()
+    t_plain_build = (time.perf_counter() - t0) * 1e3
+    order = np.argsort(ids, kind="stable")
+    bounds = np.searchsorted(ids[order], np.arange(M + 1))
+    d_qs = torch.from_numpy(q[order].view(np.int64)).to(dev)
+    v2 = torch.empty(q.size, dtype=torch.int32, device=dev)
+    f2 = torch.empty(q.size, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m_ in range(M):
+        lo, hi = int(bounds[m_]), int(bounds[m_ + 1])
+        if hi > lo:
+            F.fks_lookup_u64(maps[m_], d_qs[lo:hi], v2[lo:hi], f2[lo:hi], stream=st)
+    torch.cuda.synchronize()
+    t_plain_lookup = (time.perf_counter() - t0) * 1e3
+    for mp in maps:
+        mp.destroy()
+    total = int(off[-1])
+    return {"config": "4096 maps, sizes log-uniform 16..2^16 uint64 keys, one persistent launch; 2^24 needles, "
+                      "75% hits",
+            "keys": total, "schedule": tune["schedule"], "schedule_times_ms": tune["times_ms"],
+            "batch_build_ms": round(tb, 4), "batch_lookup_ms": round(tl, 4),
+            "batch_build_mkeys_per_s": round(total / tb / 1e3, 1),
+            "batch_lookup_mq_per_s": round(q.size / tl / 1e3, 1),
+            "one_map_per_call_build_ms": round(t_plain_build, 3),
+            "one_map_per_call_lookup_ms": round(t_plain_lookup, 3),
+            "build_speedup_vs_one_map_per_call": round(t_plain_build / tb, 2),
+            "lookup_speedup_vs_one_map_per_call": round(t_plain_lookup / tl, 2),
+            "answers_checked": ok}
+
+
+def extra_serve(dev, count=400):
+    """Config 5: Poisson stream, 20% builds (2^10..2^24 keys), 80% lookup batches (2^8..2^20,
+    50% hits), 64 GB admission budget.  Saturation from a closed-loop replay, then open-loop
+    replays at 50% and 80% of it; p50/p99 latency per request kind."""
+    from paper_2508_11443_amd import serve, workloads
+    reqs = workloads.serving_requests(count, 1000.0, 505)
+    wl = serve.Workload(reqs, [1 << 16, 1 << 20, 1 << 22, 1 << 18], 506, dev)
+    budget = 64 * (1 << 30)
+    serve.run(wl, budget, closed_loop=True)        # warm-up (graphs, pools)
+    sat, outs = serve.run(wl, budget, closed_loop=True)
+    ok = serve.check(wl, outs)
+    sat_rate = count / (sat["span_ms"] * 1e-3)     # requests per second
+    out = {"config": "Poisson stream of %d requests: 20%% builds (2^10..2^24 uint64 keys), 80%% lookup batches "
+                     "(2^8..2^20 needles, 50%% hits), 64 GB budget" % count,
+           "saturation": {"requests_per_s": round(sat_rate, 1), "queries_per_s": round(sat["queries_per_s"], 1),
+                          "lookup_p50_ms": round(sat.get("lookup_p50_ms", 0), 4),
+                          "lookup_p99_ms": round(sat.get("lookup_p99_ms", 0), 4),
+                          "build_p50_ms": round(sat.get("build_p50_ms", 0), 4),
+                          "build_p99_ms": round(sat.get("build_p99_ms", 0), 4),
+                          "launches": sat["stats"]["lookup_launches"],
+                          "graph_replays": sat["stats"]["graph_replays"]},
+           "answers_checked": ok}
+    # open-loop replays: the stream's own rate is 1000 requests/s; scale it to the target
+    for frac in (0.5, 0.8):
+        scale = frac * sat_rate / 1000.0
+        res, outs = serve.run(wl, budget, rate_scale=scale)
+        out[f"at_{int(frac * 100)}pct_saturation"] = {
+            "offered_requests_per_s": round(res["offered_rate_per_s"], 1),
+            "queries_per_s": round(res["queries_per_s"], 1),
+            "lookup_p50_ms": round(res.get("lookup_p50_ms", 0), 4),
+            "lookup_p99_ms": round(res.get("lookup_p99_ms", 0), 4),
+            "build_p50_ms": round(res.get("build_p50_ms", 0), 4),
+            "build_p99_ms": round(res.get("build_p99_ms", 0), 4)}
+        out["answers_checked"] = out["answers_checked"] and serve.check(wl, outs)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +285,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the string, batched and serving measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (known HBM bytes) for counter scaling")
     args = ap.parse_args()
@@ -275,6 +418,15 @@ def main():
         "roofline": roofline,
         "kernels": per_kernel,
     }
+    if not args.no_extras:
+        del d_keys, d_vals, d_q, d_expect, d_v, d_f
+        torch.cuda.empty_cache()
+        log("extra: strings")
+        out["strings"] = extra_strings(dev)
+        log("extra: batched build")
+        out["batched"] = extra_batch(dev)
+        log("extra: serving")
+        out["serving"] = extra_serve(dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(keys, vals, q, n, m, args.cpu_budget)

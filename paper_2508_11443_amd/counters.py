@@ -1,0 +1,86 @@
+"""Per-kernel HBM traffic from rocprofv3 counter runs.
+
+Two runs of the benchmark under ``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
+(``--output-format csv``, bench option ``--copy-calibration`` so that each run starts with
+one device copy of exactly 1 GiB) give KiB per dispatch.  Each counter is scaled by what it
+reads for that copy (1 GiB read, 1 GiB written), and the per-launch medians of the library's
+kernels at the benchmark's grid size are written to ``profiles/traffic.json`` together with
+a hash of the kernel's source file, so that ``bench.py`` reports the traffic only while the
+kernel is unchanged.
+
+    python -m paper_2508_11443_amd.counters FETCH.csv WRITE.csv profiles/traffic.json
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GIB = 1 << 30
+
+# timing name used by the library's event timer -> (kernel symbol prefix, source file)
+KERNELS = {
+    "fks_lookup_u64": ("fks::k_lookup_u64<true, true>", "paper_2508_11443_amd/csrc/lookup.hip"),
+    "fks_part_scatter": ("fks::k_dscatter<false>", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_final": ("fks::k_pfinal<false>", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_count": ("fks::k_dcount", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_sizes": ("fks::k_psizes", "paper_2508_11443_amd/csrc/partition.hip"),
+}
+
+
+def src_sha(rel: str) -> str:
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _rows(path):
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _calibration(rows, name):
+    # the 1 GiB copy: the largest copy dispatch of the run
+    vals = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"] or
+            "copy" in r["Kernel_Name"].lower()]
+    big = max(vals)
+    return GIB / (big * 1024.0)
+
+
+def summarize(fetch_csv: str, write_csv: str):
+    fr, wr = _rows(fetch_csv), _rows(write_csv)
+    sf, sw = _calibration(fr, "FETCH_SIZE"), _calibration(wr, "WRITE_SIZE")
+    out = {}
+    for timing_name, (sym, src) in KERNELS.items():
+        def per_launch(rows):
+            v = [float(r["Counter_Value"]) * 1024.0 for r in rows if r["Kernel_Name"].startswith(sym)]
+            if not v:
+                return None
+            # the benchmark's own launches are the largest grids of this kernel
+            gmax = max(int(r["Grid_Size"]) for r in rows if r["Kernel_Name"].startswith(sym))
+            v = [float(r["Counter_Value"]) * 1024.0 for r in rows
+                 if r["Kernel_Name"].startswith(sym) and int(r["Grid_Size"]) == gmax]
+            return statistics.median(v)
+        f, w = per_launch(fr), per_launch(wr)
+        if f is None or w is None:
+            continue
+        out[timing_name] = {"source_sha": src_sha(src), "source": src,
+                            "fetch_bytes_per_launch": round(f * sf), "write_bytes_per_launch": round(w * sw),
+                            "hbm_bytes_per_launch": round(f * sf + w * sw),
+                            "fetch_scale": round(sf, 4), "write_scale": round(sw, 4)}
+    return out
+
+
+def main(argv):
+    fetch_csv, write_csv, dest = argv[1:4]
+    data = summarize(fetch_csv, write_csv)
+    with open(dest, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps(data, indent=1))
+
+
+if __name__ == "__main__":
+    main(sys.argv)

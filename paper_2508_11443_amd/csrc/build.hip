@@ -599,12 +599,12 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         a.v2 = (uint32_t*)grab(4 * n);
         if (bytes) a.a2 = (uint32_t*)grab(4 * n);
     }
-    a.cntA = (uint32_t*)grab(4 * 256);
+    a.cnt = (uint32_t*)grab(4 * plan.matrix);
+    a.off = (uint32_t*)grab(4 * plan.matrix);
+    a.tsum = (uint32_t*)grab(4 * part_scan_tiles(plan));
+    a.tpre = (uint64_t*)grab(8 * (part_scan_tiles(plan) + 1));
     a.offA = (uint64_t*)grab(8 * 257);
-    a.curA = (uint64_t*)grab(8 * 256);
-    a.cntQ = (uint32_t*)grab(4 * (size_t)Q);
     a.offQ = (uint64_t*)grab(8 * ((size_t)Q + 1));
-    a.curQ = (uint64_t*)grab(8 * (size_t)Q);
     a.sqQ = (uint32_t*)grab(4 * (size_t)Q);
     a.cbase = (uint64_t*)grab(8 * ((size_t)Q + 1));
     a.sizes = (uint32_t*)grab(4 * (size_t)Q * (kPartBuckets / 8));

@@ -48,102 +48,187 @@ __device__ __forceinline__ uint32_t bucket_of(const Triple& A, uint64_t magic, u
     return fastmod(mshash(A, x), magic, n);
 }
 
-// Tiles of the key range [lo, hi): the whole input (ranges == nullptr) or the
-// partition blockIdx.y of a previous pass (ranges[p] .. ranges[p+1]).
-__device__ __forceinline__ void tile_range(const uint64_t* ranges, uint64_t n, uint64_t& lo, uint64_t& hi,
-                                           uint32_t& prefix, uint32_t bitsB) {
+// Worker blockIdx.x of W in segment blockIdx.y: segment = the whole input
+// (ranges == nullptr) or [ranges[s], ranges[s+1]); the worker owns one
+// contiguous chunk of it and walks the chunk in tiles, so that counting and
+// scattering see the keys in the same order.
+__device__ __forceinline__ void worker_range(const uint64_t* ranges, uint64_t n, uint32_t W, uint64_t& a,
+                                             uint64_t& b) {
+    uint64_t lo = 0, hi = n;
     if (ranges) {
         lo = ranges[blockIdx.y];
         hi = ranges[blockIdx.y + 1];
-        prefix = blockIdx.y << bitsB;
-    } else {
-        lo = 0;
-        hi = n;
-        prefix = 0;
     }
+    const uint64_t chunk = (hi - lo + W - 1) / W;
+    a = min(hi, lo + (uint64_t)blockIdx.x * chunk);
+    b = min(hi, a + chunk);
 }
 
-// count keys per bin: bin = ((j >> 10) >> shift) & mask, counter index prefix + bin
-__global__ __launch_bounds__(kPB) void k_pcount(const uint64_t* __restrict__ keys, uint64_t n, Triple A,
-                                                  uint64_t magic, const uint64_t* __restrict__ ranges,
-                                                  uint32_t shift, uint32_t mask, uint32_t bitsB,
-                                                  uint32_t* __restrict__ cnt) {
+// counts of one worker per bin: cnt[(segment * 256 + bin) * W + worker]
+__global__ __launch_bounds__(kPB) void k_dcount(const uint64_t* __restrict__ keys, uint64_t n, Triple A,
+                                                  uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
+                                                  uint32_t shift, uint32_t mask, uint32_t* __restrict__ cnt) {
     __shared__ uint32_t bins[kBins];
-    uint64_t lo, hi;
-    uint32_t prefix;
-    tile_range(ranges, n, lo, hi, prefix, bitsB);
-    for (uint32_t b = threadIdx.x; b < kBins; b += kPB) bins[b] = 0;
+    uint64_t a, b;
+    worker_range(ranges, n, W, a, b);
+    for (uint32_t k = threadIdx.x; k < kBins; k += kPB) bins[k] = 0;
     __syncthreads();
-    for (uint64_t ts = lo + (uint64_t)blockIdx.x * kPTile; ts < hi; ts += (uint64_t)gridDim.x * kPTile) {
+    for (uint64_t ts = a; ts < b; ts += kPTile) {
         uint64_t x[kPItems];
 #pragma unroll
         for (uint32_t k = 0; k < kPItems; ++k) {
             const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
-            x[k] = i < hi ? keys[i] : 0;
+            x[k] = i < b ? keys[i] : 0;
         }
 #pragma unroll
         for (uint32_t k = 0; k < kPItems; ++k) {
             const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
-            if (i < hi) {
+            if (i < b) {
                 const uint32_t q = bucket_of(A, magic, (uint32_t)n, x[k]) >> kPartBits;
                 atomicAdd(&bins[(q >> shift) & mask], 1u);
             }
         }
     }
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < kBins; b += kPB)
-        if (bins[b]) atomicAdd(&cnt[prefix + b], bins[b]);
+    for (uint32_t k = threadIdx.x; k < kBins; k += kPB)
+        cnt[((uint64_t)blockIdx.y * kBins + k) * W + blockIdx.x] = bins[k];
 }
 
-// scatter keys (and values, and string indices) to cursor[prefix + bin] runs
+// exclusive scan of 256 per-thread values across the block (one value per thread)
+__device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t* wsum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int q = 0; q < w; ++q) pre += wsum[q];
+    __syncthreads();
+    return pre + inc - v;
+}
+
+// Scatter of one worker's chunk: every tile is sorted by bin in LDS, then each
+// bin's run is written to consecutive addresses from the worker's scanned
+// offset (no device atomics; the output order is a function of the input).
 template <bool AUX>
-__global__ __launch_bounds__(kPB) void k_pscatter(const uint64_t* __restrict__ keys,
+__global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ aux, uint64_t n, Triple A,
-                                                    uint64_t magic, const uint64_t* __restrict__ ranges,
-                                                    uint32_t shift, uint32_t mask, uint32_t bitsB,
-                                                    uint64_t* __restrict__ cursor, uint64_t* __restrict__ keys_out,
-                                                    uint32_t* __restrict__ vals_out, uint32_t* __restrict__ aux_out) {
-    __shared__ uint32_t bins[kBins];
-    __shared__ uint64_t base[kBins];
-    uint64_t lo, hi;
-    uint32_t prefix;
-    tile_range(ranges, n, lo, hi, prefix, bitsB);
-    for (uint64_t ts = lo + (uint64_t)blockIdx.x * kPTile; ts < hi; ts += (uint64_t)gridDim.x * kPTile) {
-        for (uint32_t b = threadIdx.x; b < kBins; b += kPB) bins[b] = 0;
+                                                    uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
+                                                    uint32_t shift, uint32_t mask, const uint32_t* __restrict__ off,
+                                                    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                    uint32_t* __restrict__ aux_out) {
+    __shared__ uint64_t skey[kPTile];
+    __shared__ uint32_t sval[kPTile];
+    __shared__ uint32_t saux[AUX ? kPTile : 1];
+    __shared__ uint8_t sbin[kPTile];
+    __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
+    __shared__ uint32_t wsum[kPB / 64];
+    static_assert(kBins == kPB, "one bin per thread");
+    uint64_t a, b;
+    worker_range(ranges, n, W, a, b);
+    const uint32_t tid = threadIdx.x;
+    run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
+    for (uint64_t ts = a; ts < b; ts += kPTile) {
+        tcnt[tid] = 0;
         __syncthreads();
         uint64_t x[kPItems];
         uint32_t bin[kPItems], rank[kPItems];
 #pragma unroll
         for (uint32_t k = 0; k < kPItems; ++k) {
-            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
-            x[k] = i < hi ? keys[i] : 0;
+            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            x[k] = i < b ? keys[i] : 0;
         }
 #pragma unroll
         for (uint32_t k = 0; k < kPItems; ++k) {
-            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
-            if (i < hi) {
+            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            if (i < b) {
                 const uint32_t q = bucket_of(A, magic, (uint32_t)n, x[k]) >> kPartBits;
                 bin[k] = (q >> shift) & mask;
-                rank[k] = atomicAdd(&bins[bin[k]], 1u);
+                rank[k] = atomicAdd(&tcnt[bin[k]], 1u);
             }
         }
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < kBins; b += kPB)
-            base[b] = bins[b] ? atomicAdd((unsigned long long*)&cursor[prefix + b], (unsigned long long)bins[b]) : 0;
+        toff[tid] = block_exscan256(tcnt[tid], wsum);
         __syncthreads();
 #pragma unroll
         for (uint32_t k = 0; k < kPItems; ++k) {
-            const uint64_t i = ts + threadIdx.x + (uint64_t)k * kPB;
-            if (i < hi) {
-                const uint64_t pos = base[bin[k]] + rank[k];
-                keys_out[pos] = x[k];
-                vals_out[pos] = vals[i];
-                if (AUX) aux_out[pos] = aux ? aux[i] : (uint32_t)i;
+            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            if (i < b) {
+                const uint32_t e = toff[bin[k]] + rank[k];
+                skey[e] = x[k];
+                sval[e] = vals[i];
+                if (AUX) saux[e] = aux ? aux[i] : (uint32_t)i;
+                sbin[e] = (uint8_t)bin[k];
             }
         }
         __syncthreads();
+        const uint32_t cnt = (uint32_t)min((uint64_t)kPTile, b - ts);
+        for (uint32_t e = tid; e < cnt; e += kPB) {
+            const uint32_t bb = sbin[e];
+            const uint64_t dest = (uint64_t)run[bb] + (e - toff[bb]);
+            keys_out[dest] = skey[e];
+            vals_out[dest] = sval[e];
+            if (AUX) aux_out[dest] = saux[e];
+        }
+        __syncthreads();
+        run[tid] += tcnt[tid];
     }
+}
+
+// ---- exclusive scan of a u32 array across blocks (values sum below 2^32) --------------------
+
+constexpr uint32_t kXItems = 8;
+constexpr uint32_t kXTile = kPB * kXItems;
+
+__global__ __launch_bounds__(kPB) void k_xscan_reduce(const uint32_t* __restrict__ in, uint64_t N,
+                                                        uint32_t* __restrict__ tsum) {
+    __shared__ uint32_t wsum[kPB / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kXTile + (uint64_t)threadIdx.x * kXItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kXItems; ++k)
+        if (base + k < N) s += in[base + k];
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < kPB / 64; ++w) t += wsum[w];
+        tsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kPB) void k_xscan_down(const uint32_t* __restrict__ in, uint64_t N,
+                                                      const uint64_t* __restrict__ tpre, uint32_t* __restrict__ out) {
+    __shared__ uint32_t wsum[kPB / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kXTile + (uint64_t)threadIdx.x * kXItems;
+    uint32_t v[kXItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kXItems; ++k) {
+        v[k] = base + k < N ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t run = (uint32_t)tpre[blockIdx.x] + block_exscan256(s, wsum);
+#pragma unroll
+    for (uint32_t k = 0; k < kXItems; ++k) {
+        if (base + k < N) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// offsets of bins from a scanned count matrix: out[i] = off[((i >> bits) * 256 + (i & mask)) * W]
+// for i < count, out[count] = total
+__global__ void k_extract_offsets(const uint32_t* __restrict__ off, uint32_t W, uint32_t bits, uint32_t count,
+                                  uint64_t total, uint64_t* __restrict__ out) {
+    const uint32_t mask = (1u << bits) - 1;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= count; i += gridDim.x * blockDim.x)
+        out[i] = i < count ? (uint64_t)off[((uint64_t)(i >> bits) * kBins + (i & mask)) * W] : total;
 }
 
 // single block: exclusive prefix of cnt[0..N) into off (u64), copy into cursor,
@@ -267,9 +352,34 @@ struct FinalLds {
     uint32_t gks[kGroupsPerPart];
     uint32_t gbase[kGroupsPerPart];
     uint8_t tb[kPartBuckets];
+    uint16_t big[kPartBuckets];   // buckets of two or more keys
+    uint64_t mag[16];             // remainder magic of s^2, s = 0..15
+    uint32_t nbig;
     uint32_t wsum[2][kPB / 64];
     uint32_t flags[3];   // exhausted, dup, max_t
 };
+
+// smallest trial for a bucket of 2..8 keys held in registers: one 64-bit
+// occupancy mask, remainders by multiplication
+__device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T, uint32_t s, const uint64_t (&kx)[8],
+                                                    uint64_t M) {
+    const uint32_t s2 = s * s;
+    for (uint32_t t = 0; t < T; ++t) {
+        const Triple c = C[t];
+        uint64_t m = 0;
+        bool collide = false;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+            if (i < s && !collide) {
+                const uint64_t bit = 1ull << fastmod(mshash(c, kx[i]), M, s2);
+                collide = (m & bit) != 0;
+                m |= bit;
+            }
+        }
+        if (!collide) return t;
+    }
+    return T;
+}
 
 template <bool BYTES>
 __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
@@ -336,67 +446,96 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
     if (fast) {
         // stage the partition's keys; ranks come from a second LDS histogram
         for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
+        for (uint32_t b = tid; b < kPartBuckets; b += kPB) L.tb[b] = 0;
+        if (tid < 16) L.mag[tid] = tid ? fastmod_magic(tid * tid) : 0;
+        if (tid == 0) L.nbig = 0;
         __syncthreads();
-        for (uint32_t i = tid; i < nq; i += kPB) {
-            const uint64_t x = keys[k0 + i];
-            L.key[i] = x;
-            L.val[i] = vals[k0 + i];
-            if (BYTES) L.aux[i] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
-            const uint32_t lb = bucket_of(A, magic, (uint32_t)n, x) & (kPartBuckets - 1);
-            L.lb[i] = (uint16_t)lb;
-            const uint32_t sh = 4 * (lb & 7u);
-            L.rank[i] = (uint8_t)((atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u);
+        constexpr uint32_t KPT = kFinalKeyCap / kPB;
+        uint64_t xk[KPT];
+        uint32_t vk[KPT], ak[KPT];
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) {
+            const uint32_t i = tid + k * kPB;
+            if (i < nq) {
+                xk[k] = keys[k0 + i];
+                vk[k] = vals[k0 + i];
+                if (BYTES) ak[k] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
+            }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) {
+            const uint32_t i = tid + k * kPB;
+            if (i < nq) {
+                L.key[i] = xk[k];
+                L.val[i] = vk[k];
+                if (BYTES) L.aux[i] = ak[k];
+                const uint32_t lb = bucket_of(A, magic, (uint32_t)n, xk[k]) & (kPartBuckets - 1);
+                L.lb[i] = (uint16_t)lb;
+                const uint32_t sh = 4 * (lb & 7u);
+                L.rank[i] = (uint8_t)((atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u);
+            }
         }
         __syncthreads();
-        for (uint32_t i = tid; i < nq; i += kPB) {
-            const uint32_t lb = L.lb[i], g = lb >> 3;
-            L.perm[L.gks[g] + prefix_cnt(L.words[g], lb & 7u) + L.rank[i]] = (uint16_t)i;
+        // group by bucket; a lone key owns its bucket's single cell; the first key of a
+        // larger bucket enlists the bucket for the level-two search
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) {
+            const uint32_t i = tid + k * kPB;
+            if (i < nq) {
+                const uint32_t lb = L.lb[i], g = lb >> 3, kk = lb & 7u, w = L.words[g];
+                const uint32_t r = L.rank[i], s = nib(w, kk);
+                L.perm[L.gks[g] + prefix_cnt(w, kk) + r] = (uint16_t)i;
+                if (s == 1) L.smap[L.gbase[g] + prefix_sq(w, kk)] = (uint16_t)i;
+                else if (r == 0) L.big[atomicAdd(&L.nbig, 1u)] = (uint16_t)lb;
+            }
         }
         __syncthreads();
-        for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
+        const uint32_t nb = L.nbig;
+        for (uint32_t j = tid; j < nb; j += kPB) {
+            const uint32_t b = L.big[j];
             const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
-            const uint32_t s = nib(w, kk);
+            const uint32_t s = nib(w, kk), s2 = s * s;
             const uint32_t kst = L.gks[g] + prefix_cnt(w, kk);
             const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
-            uint32_t t = 0;
-            bool exhausted = false;
-            if (s >= 2) {
+            const uint64_t M = L.mag[s];
+            uint32_t t;
+            if (s <= 8) {
+                uint64_t kx[8];
+#pragma unroll
+                for (uint32_t i = 0; i < 8; ++i) kx[i] = i < s ? L.key[L.perm[kst + i]] : 0;
+                t = min_trial_small(LC, T, s, kx, M);
+            } else {
                 t = min_trial(LC, T, s, [&](uint32_t i) { return L.key[L.perm[kst + i]]; });
-                exhausted = t == T;
             }
-            const uint32_t s2 = s * s;
-            if (s >= 1) {
-                if (!exhausted) {
-                    for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = 0xFFFFu;
-                    const Triple c = LC[t];
-                    for (uint32_t i = 0; i < s; ++i) {
-                        const uint16_t who = L.perm[kst + i];
-                        L.smap[off + mshash(c, L.key[who]) % s2] = who;
-                    }
-                    uint16_t first = 0;
-                    for (uint32_t p = 0; p < s2; ++p)
-                        if (L.smap[off + p] != 0xFFFFu) {
-                            first = L.smap[off + p];
-                            break;
-                        }
-                    for (uint32_t p = 0; p < s2; ++p)
-                        if (L.smap[off + p] == 0xFFFFu) L.smap[off + p] = first;
-                } else {
-                    for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = L.perm[kst];
-                    bool dup = false;
-                    for (uint32_t a = 0; a < s; ++a)
-                        for (uint32_t b2 = a + 1; b2 < s; ++b2) {
-                            const uint16_t ia = L.perm[kst + a], ib = L.perm[kst + b2];
-                            if (BYTES) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
-                            else dup |= L.key[ia] == L.key[ib];
-                        }
-                    atomicOr(&L.flags[0], 1u);
-                    if (dup) atomicOr(&L.flags[1], 1u);
+            if (t < T) {
+                for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = 0xFFFFu;
+                const Triple c = LC[t];
+                for (uint32_t i = 0; i < s; ++i) {
+                    const uint16_t who = L.perm[kst + i];
+                    L.smap[off + fastmod(mshash(c, L.key[who]), M, s2)] = who;
                 }
+                uint16_t first = 0;
+                for (uint32_t p = 0; p < s2; ++p)
+                    if (L.smap[off + p] != 0xFFFFu) {
+                        first = L.smap[off + p];
+                        break;
+                    }
+                for (uint32_t p = 0; p < s2; ++p)
+                    if (L.smap[off + p] == 0xFFFFu) L.smap[off + p] = first;
+                L.tb[b] = (uint8_t)t;
+                if (t) atomicMax(&L.flags[2], t);
+            } else {
+                for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = L.perm[kst];
+                bool dup = false;
+                for (uint32_t a2 = 0; a2 < s; ++a2)
+                    for (uint32_t b2 = a2 + 1; b2 < s; ++b2) {
+                        const uint16_t ia = L.perm[kst + a2], ib = L.perm[kst + b2];
+                        if (BYTES) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
+                        else dup |= L.key[ia] == L.key[ib];
+                    }
+                atomicOr(&L.flags[0], 1u);
+                if (dup) atomicOr(&L.flags[1], 1u);
             }
-            if (exhausted) t = 0;
-            if (t) atomicMax(&L.flags[2], t);
-            L.tb[b] = (uint8_t)t;
         }
         __syncthreads();
         for (uint32_t p = tid; p < Sq; p += kPB) {
@@ -505,30 +644,47 @@ PartPlan part_plan(uint64_t n) {
     uint32_t bits = 0;
     while ((1ull << bits) < P.Q) ++bits;
     P.bits_q = bits;
+    auto clampu = [](uint64_t v, uint64_t lo, uint64_t hi) { return (uint32_t)(v < lo ? lo : v > hi ? hi : v); };
+    P.W1 = clampu((n + 4 * kPTile - 1) / (4 * kPTile), 1, 4096);
     if (P.Q <= 1) {
         P.passes = 0;
     } else if (bits <= 8) {
         P.passes = 1;
-        P.shiftA = 0;
         P.binsA = P.Q;
-        P.bitsB = 0;
     } else {
         P.passes = 2;
         P.shiftA = bits - 8;
         P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
         P.bitsB = P.shiftA;
+        P.W2 = clampu((n / P.binsA + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
     }
+    uint64_t m1 = (uint64_t)kBins * P.W1;
+    uint64_t m2 = P.passes == 2 ? (uint64_t)P.binsA * kBins * P.W2 : 0;
+    P.matrix = m1 > m2 ? m1 : m2;
     return P;
 }
 
-static unsigned tiles_of(uint64_t n) {
-    uint64_t t = (n + kPTile - 1) / kPTile;
-    return (unsigned)(t ? t : 1);
+uint64_t part_scan_tiles(const PartPlan& P) { return (P.matrix + kXTile - 1) / kXTile; }
+
+static void scan_matrix(const PartArgs& a, uint64_t N, hipStream_t st) {
+    const uint32_t nt = (uint32_t)((N + kXTile - 1) / kXTile);
+    hipLaunchKernelGGL(k_xscan_reduce, nt, kPB, 0, st, a.cnt, N, a.tsum);
+    hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.tsum, nt, a.tpre, nullptr, nullptr);
+    hipLaunchKernelGGL(k_xscan_down, nt, kPB, 0, st, a.cnt, N, a.tpre, a.off);
 }
 
-// Runs passes for attempt A; on return (stream-ordered) offQ, the partitioned
-// records (pointed to by *rk/*rv/*ra), per-partition squares and their scan
-// (cbase, total S in *S_dev) and the sizes words are in place.
+template <bool AUX>
+static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin, const uint32_t* ain,
+                    const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift, uint32_t mask, uint64_t* kout,
+                    uint32_t* vout, uint32_t* aout, hipStream_t st) {
+    FKS_TIMED("fks_part_scatter", st,
+              hipLaunchKernelGGL(k_dscatter<AUX>, grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
+                                 shift, mask, a.off, kout, vout, aout));
+}
+
+// Runs the partition passes of one attempt; stream-ordered outputs: offQ, the
+// records in partition order (o.keys/vals/aux), the size words, the partition
+// sums of squares, their scan (cbase) and the total S (*S_dev).
 int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     const PartPlan P = part_plan(a.n);
     const uint64_t n = a.n;
@@ -538,64 +694,42 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     o.vals = a.vals;
     o.aux = nullptr;
     o.aux_is_pos = 1;
-    hipError_t e = hipSuccess;
-    // fill counters with a kernel (no memset nodes in streams that might be captured)
-    auto zero = [&](void* p, size_t words) {
-        hipLaunchKernelGGL(k_zero_words, (unsigned)((words + 255) / 256 > 4096 ? 4096 : (words + 255) / 256 + 1),
-                           256, 0, st, (uint32_t*)p, (uint64_t)words);
+    auto count = [&](const uint64_t* kin, const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift,
+                     uint32_t mask) {
+        FKS_TIMED("fks_part_count", st,
+                  hipLaunchKernelGGL(k_dcount, grid, kPB, 0, st, kin, n, a.A, a.magic, ranges, W, shift, mask,
+                                     a.cnt));
     };
     if (P.passes == 0) {
-        // one partition: offQ = {0, n}
         hipLaunchKernelGGL(k_set_range, 1, 64, 0, st, a.offQ, n);
     } else if (P.passes == 1) {
-        zero(a.cntQ, P.Q);
-        FKS_TIMED("fks_part_count", st,
-                  hipLaunchKernelGGL(k_pcount, std::min(tiles_of(n), 2048u), kPB, 0, st, a.keys, n, a.A, a.magic,
-                                     nullptr, 0u, 255u, 0u, a.cntQ));
-        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.cntQ, P.Q, a.offQ, a.curQ, nullptr);
-        if (bytes)
-            FKS_TIMED("fks_part_scatter", st,
-                      hipLaunchKernelGGL(k_pscatter<true>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n, a.A,
-                                         a.magic, nullptr, 0u, 255u, 0u, a.curQ, a.k2, a.v2, a.a2));
-        else
-            FKS_TIMED("fks_part_scatter", st,
-                      hipLaunchKernelGGL(k_pscatter<false>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n,
-                                         a.A, a.magic, nullptr, 0u, 255u, 0u, a.curQ, a.k2, a.v2, a.a2));
+        count(a.keys, nullptr, dim3(P.W1, 1), P.W1, 0, 255);
+        scan_matrix(a, (uint64_t)kBins * P.W1, st);
+        if (bytes) scatter<true>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, 0, 255, a.k2, a.v2, a.a2, st);
+        else scatter<false>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, 0, 255, a.k2, a.v2, a.a2, st);
+        hipLaunchKernelGGL(k_extract_offsets, (P.Q + 256) / 256, 256, 0, st, a.off, P.W1, 8u, P.Q, n, a.offQ);
         o.keys = a.k2;
         o.vals = a.v2;
         o.aux = a.a2;
         o.aux_is_pos = bytes ? 0 : 1;
     } else {
-        zero(a.cntA, 256);
-        zero(a.cntQ, P.Q);
-        FKS_TIMED("fks_part_count", st,
-                  hipLaunchKernelGGL(k_pcount, std::min(tiles_of(n), 2048u), kPB, 0, st, a.keys, n, a.A, a.magic,
-                                     nullptr, P.shiftA, 255u, 0u, a.cntA));
-        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.cntA, P.binsA, a.offA, a.curA, nullptr);
+        count(a.keys, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255);
+        scan_matrix(a, (uint64_t)kBins * P.W1, st);
         if (bytes)
-            FKS_TIMED("fks_part_scatter", st,
-                      hipLaunchKernelGGL(k_pscatter<true>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n, a.A,
-                                         a.magic, nullptr, P.shiftA, 255u, 0u, a.curA, a.k1, a.v1, a.a1));
+            scatter<true>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1, a.a1,
+                          st);
         else
-            FKS_TIMED("fks_part_scatter", st,
-                      hipLaunchKernelGGL(k_pscatter<false>, tiles_of(n), kPB, 0, st, a.keys, a.vals, nullptr, n,
-                                         a.A, a.magic, nullptr, P.shiftA, 255u, 0u, a.curA, a.k1, a.v1, a.a1));
-        // second level, inside every first-level partition
+            scatter<false>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1,
+                           a.a1, st);
+        hipLaunchKernelGGL(k_extract_offsets, (P.binsA + 256) / 256, 256, 0, st, a.off, P.W1, 8u, P.binsA, n, a.offA);
         const uint32_t maskB = (1u << P.bitsB) - 1;
-        const unsigned per = std::max(1u, std::min(64u, tiles_of(n / std::max(1u, P.binsA)) + 1));
-        dim3 grid2(per, P.binsA);
-        FKS_TIMED("fks_part_count", st,
-                  hipLaunchKernelGGL(k_pcount, grid2, kPB, 0, st, a.k1, n, a.A, a.magic, a.offA, 0u, maskB, P.bitsB,
-                                     a.cntQ));
-        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.cntQ, P.Q, a.offQ, a.curQ, nullptr);
+        count(a.k1, a.offA, dim3(P.W2, P.binsA), P.W2, 0, maskB);
+        scan_matrix(a, (uint64_t)P.binsA * kBins * P.W2, st);
         if (bytes)
-            FKS_TIMED("fks_part_scatter", st,
-                      hipLaunchKernelGGL(k_pscatter<true>, grid2, kPB, 0, st, a.k1, a.v1, a.a1, n, a.A, a.magic,
-                                         a.offA, 0u, maskB, P.bitsB, a.curQ, a.k2, a.v2, a.a2));
+            scatter<true>(a, a.k1, a.v1, a.a1, a.offA, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2, a.v2, a.a2, st);
         else
-            FKS_TIMED("fks_part_scatter", st,
-                      hipLaunchKernelGGL(k_pscatter<false>, grid2, kPB, 0, st, a.k1, a.v1, nullptr, n, a.A, a.magic,
-                                         a.offA, 0u, maskB, P.bitsB, a.curQ, a.k2, a.v2, a.a2));
+            scatter<false>(a, a.k1, a.v1, nullptr, a.offA, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2, a.v2, a.a2, st);
+        hipLaunchKernelGGL(k_extract_offsets, (P.Q + 256) / 256, 256, 0, st, a.off, P.W2, P.bitsB, P.Q, n, a.offQ);
         o.keys = a.k2;
         o.vals = a.v2;
         o.aux = a.a2;
@@ -605,7 +739,7 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
               hipLaunchKernelGGL(k_psizes, P.Q, kPB, 0, st, o.keys, n, a.A, a.magic, a.offQ, a.sizes, a.G, a.sqQ,
                                  a.oversize));
     hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.sqQ, P.Q, a.cbase, nullptr, a.S_dev);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
 

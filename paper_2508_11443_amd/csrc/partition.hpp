@@ -18,6 +18,8 @@ struct PartPlan {
     uint32_t shiftA;   // first-level bin = q >> shiftA
     uint32_t binsA;    // first-level bins
     uint32_t bitsB;    // second-level bin = q & (2^bitsB - 1)
+    uint32_t W1, W2;   // workers of the first pass / per first-level bin in the second pass
+    uint64_t matrix;   // entries of the largest count matrix
 };
 
 // Inputs, scratch and outputs of one attempt (device pointers).
@@ -32,10 +34,12 @@ struct PartArgs {
     uint64_t *k1, *k2;          // partitioned keys after pass 1 / pass 2
     uint32_t *v1, *v2;          // values
     uint32_t *a1, *a2;          // string indices (string maps)
-    uint32_t* cntA;             // 256 first-level counters
-    uint64_t *offA, *curA;      // 257 offsets, 256 cursors
-    uint32_t* cntQ;             // Q partition counters
-    uint64_t *offQ, *curQ;      // Q+1 offsets, Q cursors
+    uint32_t* cnt;              // per-worker bin counts (plan.matrix entries)
+    uint32_t* off;              // their exclusive scan
+    uint32_t* tsum;             // scan tile sums
+    uint64_t* tpre;             // scanned tile sums
+    uint64_t* offA;             // 257 first-level bin offsets
+    uint64_t* offQ;             // Q+1 partition offsets
     uint32_t* sqQ;              // Q sums of squared sizes
     uint64_t* cbase;            // Q+1 cell bases
     uint32_t* sizes;            // G size words (the headers' second word)
@@ -52,6 +56,7 @@ struct PartOut {
 };
 
 PartPlan part_plan(uint64_t n);
+uint64_t part_scan_tiles(const PartPlan& P);
 int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o);
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, hipStream_t st);
