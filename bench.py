@@ -375,6 +375,10 @@ def main():
 
     hit_frac = float(expect.mean())
     S = info["S"]
+    # the device's random-read ceiling, measured now on a buffer as large as the table
+    probes = 1 << 27
+    probe_ms = {w: fks.fks_probe_random_reads(2 << 30, probes, w, stream=stream) for w in (16, 64)}
+    accesses = m * (1 + hit_frac + (1 - hit_frac) * nonempty_frac)
     per_kernel = {}
     for name, (launches, ms) in prof.items():
         avg = ms / max(launches, 1)
@@ -414,11 +418,25 @@ def main():
         "lookup_pct_hbm": round(100 * lookup_alg / (lookup_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
         "table": {"S_over_n": round(S / n, 4), "r": info["r"], "max_t": info["max_t"],
                   "nonempty_bucket_frac": round(nonempty_frac, 4)},
+        "random_access": {
+            "lookup_random_reads_per_query": round(accesses / m, 4),
+            "lookup_G_reads_per_s": round(accesses / (lookup_ms * 1e-3) / 1e9, 2),
+            "probe_G_reads_per_s_16B": round(probes / (probe_ms[16] * 1e-3) / 1e9, 2),
+            "probe_G_reads_per_s_64B": round(probes / (probe_ms[64] * 1e-3) / 1e9, 2),
+            "lookup_frac_of_probe_ceiling": round((accesses / (lookup_ms * 1e-3)) / (probes / (probe_ms[16] * 1e-3)), 4)},
         "answers_checked": ok,
         "roofline": roofline,
         "kernels": per_kernel,
     }
     if not args.no_extras:
+        # the paper's own level-two formulation (Section 2.5 rounds) on the same keys
+        log("extra: flattened-rounds schedule")
+        tr = _median_ms(lambda: fks.fks_build_u64(d_keys, d_vals, SEED, stream=stream, schedule=1), 3, stream)
+        hr = fks.fks_export(fks.fks_build_u64(d_keys, d_vals, SEED, stream=stream, schedule=1))[0]
+        hb = fks.fks_export(fks.fks_build_u64(d_keys, d_vals, SEED, stream=stream))[0]
+        out["rounds_schedule"] = {"build_ms": round(tr, 4), "per_bucket_build_ms": round(build_ms, 4),
+                                  "slowdown": round(tr / build_ms, 2),
+                                  "same_header_bytes": bool((hr == hb).all())}
         del d_keys, d_vals, d_q, d_expect, d_v, d_f
         torch.cuda.empty_cache()
         log("extra: strings")

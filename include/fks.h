@@ -65,12 +65,16 @@ extern "C" {
  *     (default 64, range 1..256; make_2 of Section 2.3 retries without bound,
  *     expected at most 2 trials).
  * R : level-one attempts before FKS_EBUILD (default 16, range 1..1024).
+ * schedule : how single-map builds search level two (the table is the same):
+ *     0 = every bucket searched by one lane over its keys in LDS (default);
+ *     1 = the paper's flattened rounds (Section 2.5): round t tries triple t
+ *         on every unfinished bucket with a histogram over the flat cells.
  * Attempts also reject any bucket of more than 15 keys.                     */
 typedef struct fks_params {
     uint32_t c;
     uint32_t T;
     uint32_t R;
-    uint32_t reserved;   /* must be 0 */
+    uint32_t schedule;
 } fks_params;
 
 typedef struct fks_map fks_map;       /* opaque; owns all of its device memory */
@@ -107,6 +111,17 @@ void fks_params_default(fks_params* p);
  */
 int fks_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint64_t seed,
                   const fks_params* params, void* stream, fks_map** out);
+
+/*
+ * from_array (Figure 2) for 64-bit keys: like fks_build_u64, but the u input
+ * pairs may repeat a key.  The paper leaves open which value a repeated key
+ * keeps; here it is the value of its first occurrence (lowest input index).
+ * The map holds the distinct keys (fks_info reports their number as n) and
+ * its table equals fks_build_u64 over those keys with their kept values.
+ * Errors: as fks_build_u64 (never FKS_EDUPKEY); u < 2^30.
+ */
+int fks_build_u64_from_array(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t u, uint64_t seed,
+                             const fks_params* params, void* stream, fks_map** out);
 
 /*
  * from_array_nodup for byte-string keys (Section 3.1 contexts, Section 3.3.1
@@ -272,6 +287,14 @@ int fks_server_stats(fks_server* srv, fks_server_stats_t* stats);
 const fks_map* fks_server_map(fks_server* srv, uint32_t map_id);
 /* Waits for every submitted request, then releases the server and its maps. */
 void fks_server_destroy(fks_server* srv);
+
+/* ---- device random-access ceiling ----------------------------------------
+ * Times `probes` independent random reads of width_bytes (16, 32, 64 or 128)
+ * from a buffer of about buffer_bytes (allocated and released inside), after
+ * one warm-up pass; *ms_out receives the time of the second pass.  The rate
+ * probes / time is the ceiling that one- and two-probe lookups run against. */
+int fks_probe_random_reads(uint64_t buffer_bytes, uint64_t probes, uint32_t width_bytes, void* stream,
+                           double* ms_out);
 
 /* ---- kernel timing ------------------------------------------------------
  * When enabled, every kernel the library launches is bracketed by two HIP

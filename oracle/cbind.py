@@ -56,6 +56,8 @@ def liboracle():
         lib.oracle_fingerprint.argtypes = [vp, u64, u64]
         lib.oracle_build_u64.restype = i32
         lib.oracle_build_u64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+        lib.oracle_build_u64_dedup.restype = i32
+        lib.oracle_build_u64_dedup.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
         lib.oracle_build_bytes.restype = i32
         lib.oracle_build_bytes.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
         lib.oracle_lookup_u64.restype = i32
@@ -167,6 +169,19 @@ def build_u64(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int
     assert k.size == v.size
     h = ctypes.c_void_p()
     rc = liboracle().oracle_build_u64(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
+    if rc:
+        raise OracleError(rc)
+    return OracleMap(h.value)
+
+
+def build_u64_dedup(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int = 64,
+                    R: int = 16) -> OracleMap:
+    """from_array: repeated keys keep the value of their first occurrence."""
+    k = np.ascontiguousarray(keys, np.uint64)
+    v = np.ascontiguousarray(vals, np.uint32)
+    assert k.size == v.size
+    h = ctypes.c_void_p()
+    rc = liboracle().oracle_build_u64_dedup(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
     if rc:
         raise OracleError(rc)
     return OracleMap(h.value)

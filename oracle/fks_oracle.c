@@ -419,6 +419,46 @@ int oracle_build_bytes(const int64_t* offsets, const uint8_t* bytes, const uint3
     return OR_EBUILD;
 }
 
+/* ---- from_array: the constructor that tolerates duplicate keys ---------
+ * Figure 2 gives from_array beside from_array_nodup without fixing which
+ * value a repeated key keeps; reading: the value of its first occurrence
+ * (lowest input index).  The distinct keys then go through from_array_nodup;
+ * the table does not depend on their order. */
+
+static const uint64_t* or_sort_keys;
+
+static int or_cmp_key_index(const void* a, const void* b)
+{
+    uint64_t i = *(const uint64_t*)a, j = *(const uint64_t*)b;
+    uint64_t ki = or_sort_keys[i], kj = or_sort_keys[j];
+    if (ki != kj) return ki < kj ? -1 : 1;
+    return i < j ? -1 : (i > j ? 1 : 0);
+}
+
+int oracle_build_u64_dedup(const uint64_t* keys, const uint32_t* vals, uint64_t u, uint64_t sigma,
+                           uint32_t c, uint32_t T, uint32_t R, oracle_map** out)
+{
+    if (u >= (1ULL << 32)) return OR_EINVAL;
+    uint64_t* idx = malloc(sizeof(uint64_t) * (u ? u : 1));
+    uint64_t* dk = malloc(sizeof(uint64_t) * (u ? u : 1));
+    uint32_t* dv = malloc(sizeof(uint32_t) * (u ? u : 1));
+    if (!idx || !dk || !dv) { free(idx); free(dk); free(dv); return OR_ENOMEM; }
+    for (uint64_t i = 0; i < u; ++i) idx[i] = i;
+    or_sort_keys = keys;
+    qsort(idx, u, sizeof(uint64_t), or_cmp_key_index);
+    uint64_t n = 0;
+    for (uint64_t k = 0; k < u; ++k) {
+        if (k == 0 || keys[idx[k]] != keys[idx[k - 1]]) {
+            dk[n] = keys[idx[k]];
+            dv[n] = vals[idx[k]];
+            ++n;
+        }
+    }
+    int rc = oracle_build_u64(dk, dv, n, sigma, c, T, R, out);
+    free(idx); free(dk); free(dv);
+    return rc;
+}
+
 /* ---- lookup: the membership test of Section 2.2 over the built table ---- */
 
 static int64_t or_probe(const oracle_map* M, uint64_t x)

@@ -531,7 +531,7 @@ extern "C" int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_val
     fks_params P;
     fks_params_default(&P);
     if (params) P = *params;
-    if (P.c < 1 || P.c > 16 || P.T < 1 || P.T > kTMax || P.R < 1 || P.R > 1024 || P.reserved) return FKS_EINVAL;
+    if (P.c < 1 || P.c > 16 || P.T < 1 || P.T > kTMax || P.R < 1 || P.R > 1024 || P.schedule != 0) return FKS_EINVAL;
     if (h_map_offsets[0] != 0) return FKS_EINVAL;
     uint64_t total = h_map_offsets[M];
     if (total && (!d_keys || !d_vals)) return FKS_EINVAL;

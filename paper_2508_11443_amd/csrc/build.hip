@@ -28,6 +28,7 @@
 #include "fks_internal.hpp"
 #include "partition.hpp"
 #include "prof.hpp"
+#include "rounds.hpp"
 
 #include <cstdlib>
 
@@ -544,7 +545,7 @@ static int check_params(uint64_t n, const fks_params* p, fks_params& out) {
     if (p) out = *p;
     if (n >= (1ull << 30)) return FKS_EINVAL;
     if (out.c < 1 || out.c > 16 || out.T < 1 || out.T > kTMax || out.R < 1 || out.R > 1024 ||
-        out.reserved != 0)
+        out.schedule > 1)
         return FKS_EINVAL;
     if ((uint64_t)out.c * n >= (1ull << 32)) return FKS_EINVAL;
     return FKS_OK;
@@ -644,7 +645,30 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             rc = FKS_ENOMEM;
             break;
         }
-        rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off, M->ctx_bytes, st);
+        const uint8_t* given_t = nullptr;
+        if (P.schedule == 1) {
+            // the paper's flattened rounds decide every bucket's trial; the table
+            // write below then only places the keys
+            uint8_t* tb = (uint8_t*)dev_alloc(4 * ((n + 3) / 4), st);
+            if (!tb) {
+                dev_free(slots, st);
+                rc = FKS_ENOMEM;
+                break;
+            }
+            owned.push_back(tb);
+            hipLaunchKernelGGL(k_fill_u32, grid_for((n + 3) / 4, kBlock, 8192), kBlock, 0, st, (uint32_t*)tb,
+                               (n + 3) / 4, 0u);
+            bool exhausted = false;
+            rc = rounds_search(o.keys, n, S, A, M->magic_n, a.sizes, Ch, P.T, tb, &exhausted, st);
+            if (rc) {
+                dev_free(slots, st);
+                break;
+            }
+            // a bucket left after T rounds goes through the per-bucket search, which
+            // reports the exhaustion (and any duplicate keys) exactly as it would alone
+            if (!exhausted) given_t = tb;
+        }
+        rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off, M->ctx_bytes, given_t, st);
         if (rc == FKS_OK) {
             hipError_t e = hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);

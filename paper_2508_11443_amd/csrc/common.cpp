@@ -60,7 +60,7 @@ void fks_params_default(fks_params* p) {
     p->c = 4;
     p->T = 64;
     p->R = 16;
-    p->reserved = 0;
+    p->schedule = 0;
 }
 
 const char* fks_strerror(int code) {

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "fks_internal.hpp"
 #include "partition.hpp"
@@ -27,8 +28,8 @@ constexpr uint32_t kPB = 256;                 // threads per block, partition pa
 constexpr uint32_t kPItems = 16;              // keys per thread per tile
 constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
 constexpr uint32_t kBins = 256;               // bins per scatter pass
-constexpr uint32_t kFinalKeyCap = 1536;       // keys of one partition held in LDS (mean 1024)
-constexpr uint32_t kFinalCellCap = 4096;      // cells of one partition staged in LDS (mean ~2048)
+constexpr uint32_t kFinalKeyCap = 1280;       // keys of one partition held in LDS (mean 1024, sd 32)
+constexpr uint32_t kFinalCellCap = 3072;      // cells of one partition staged in LDS (mean <= 2048, sd ~106)
 constexpr uint32_t kGroupsPerPart = kPartBuckets / 8;
 
 __global__ void k_zero_words(uint32_t* __restrict__ p, uint64_t count) {
@@ -114,7 +115,7 @@ __device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t* wsum) 
 // Scatter of one worker's chunk: every tile is sorted by bin in LDS, then each
 // bin's run is written to consecutive addresses from the worker's scanned
 // offset (no device atomics; the output order is a function of the input).
-template <bool AUX>
+template <bool AUX, uint32_t ITEMS>
 __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ aux, uint64_t n, Triple A,
@@ -122,10 +123,10 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
                                                     uint32_t shift, uint32_t mask, const uint32_t* __restrict__ off,
                                                     uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                     uint32_t* __restrict__ aux_out) {
-    __shared__ uint64_t skey[kPTile];
-    __shared__ uint32_t sval[kPTile];
-    __shared__ uint32_t saux[AUX ? kPTile : 1];
-    __shared__ uint8_t sbin[kPTile];
+    __shared__ uint64_t skey[(kPB * ITEMS)];
+    __shared__ uint32_t sval[(kPB * ITEMS)];
+    __shared__ uint32_t saux[AUX ? (kPB * ITEMS) : 1];
+    __shared__ uint8_t sbin[(kPB * ITEMS)];
     __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
     __shared__ uint32_t wsum[kPB / 64];
     static_assert(kBins == kPB, "one bin per thread");
@@ -133,18 +134,18 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
     worker_range(ranges, n, W, a, b);
     const uint32_t tid = threadIdx.x;
     run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
-    for (uint64_t ts = a; ts < b; ts += kPTile) {
+    for (uint64_t ts = a; ts < b; ts += (kPB * ITEMS)) {
         tcnt[tid] = 0;
         __syncthreads();
-        uint64_t x[kPItems];
-        uint32_t bin[kPItems], rank[kPItems];
+        uint64_t x[ITEMS];
+        uint32_t bin[ITEMS], rank[ITEMS];
 #pragma unroll
-        for (uint32_t k = 0; k < kPItems; ++k) {
+        for (uint32_t k = 0; k < ITEMS; ++k) {
             const uint64_t i = ts + tid + (uint64_t)k * kPB;
             x[k] = i < b ? keys[i] : 0;
         }
 #pragma unroll
-        for (uint32_t k = 0; k < kPItems; ++k) {
+        for (uint32_t k = 0; k < ITEMS; ++k) {
             const uint64_t i = ts + tid + (uint64_t)k * kPB;
             if (i < b) {
                 const uint32_t q = bucket_of(A, magic, (uint32_t)n, x[k]) >> kPartBits;
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
         toff[tid] = block_exscan256(tcnt[tid], wsum);
         __syncthreads();
 #pragma unroll
-        for (uint32_t k = 0; k < kPItems; ++k) {
+        for (uint32_t k = 0; k < ITEMS; ++k) {
             const uint64_t i = ts + tid + (uint64_t)k * kPB;
             if (i < b) {
                 const uint32_t e = toff[bin[k]] + rank[k];
@@ -167,13 +168,73 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
             }
         }
         __syncthreads();
-        const uint32_t cnt = (uint32_t)min((uint64_t)kPTile, b - ts);
+        const uint32_t cnt = (uint32_t)min((uint64_t)(kPB * ITEMS), b - ts);
         for (uint32_t e = tid; e < cnt; e += kPB) {
             const uint32_t bb = sbin[e];
             const uint64_t dest = (uint64_t)run[bb] + (e - toff[bb]);
             keys_out[dest] = skey[e];
             vals_out[dest] = sval[e];
             if (AUX) aux_out[dest] = saux[e];
+        }
+        __syncthreads();
+        run[tid] += tcnt[tid];
+    }
+}
+
+// Same scatter, staging only each slot's source position within the tile (the
+// records are read again, from L2, when the runs are written): a small LDS
+// footprint, so more workgroups per CU.
+template <bool AUX, uint32_t ITEMS>
+__global__ __launch_bounds__(kPB) void k_dscatter_p(const uint64_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const uint32_t* __restrict__ aux, uint64_t n, Triple A,
+                                                      uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
+                                                      uint32_t shift, uint32_t mask, const uint32_t* __restrict__ off,
+                                                      uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                      uint32_t* __restrict__ aux_out) {
+    constexpr uint32_t TILE = kPB * ITEMS;
+    __shared__ uint16_t ssrc[TILE];
+    __shared__ uint8_t sbin[TILE];
+    __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
+    __shared__ uint32_t wsum[kPB / 64];
+    uint64_t a, b;
+    worker_range(ranges, n, W, a, b);
+    const uint32_t tid = threadIdx.x;
+    run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
+    for (uint64_t ts = a; ts < b; ts += TILE) {
+        tcnt[tid] = 0;
+        __syncthreads();
+        uint32_t bin[ITEMS], rank[ITEMS];
+#pragma unroll
+        for (uint32_t k = 0; k < ITEMS; ++k) {
+            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            if (i < b) {
+                const uint32_t q = bucket_of(A, magic, (uint32_t)n, keys[i]) >> kPartBits;
+                bin[k] = (q >> shift) & mask;
+                rank[k] = atomicAdd(&tcnt[bin[k]], 1u);
+            }
+        }
+        __syncthreads();
+        toff[tid] = block_exscan256(tcnt[tid], wsum);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < ITEMS; ++k) {
+            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            if (i < b) {
+                const uint32_t e = toff[bin[k]] + rank[k];
+                ssrc[e] = (uint16_t)(tid + k * kPB);
+                sbin[e] = (uint8_t)bin[k];
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = (uint32_t)min((uint64_t)TILE, b - ts);
+        for (uint32_t e = tid; e < cnt; e += kPB) {
+            const uint32_t bb = sbin[e];
+            const uint64_t src = ts + ssrc[e];
+            const uint64_t dest = (uint64_t)run[bb] + (e - toff[bb]);
+            keys_out[dest] = keys[src];
+            vals_out[dest] = vals[src];
+            if (AUX) aux_out[dest] = aux ? aux[src] : (uint32_t)src;
         }
         __syncthreads();
         run[tid] += tcnt[tid];
@@ -343,9 +404,7 @@ struct FinalLds {
     uint64_t key[kFinalKeyCap];
     uint32_t val[kFinalKeyCap];
     uint32_t aux[BYTES ? kFinalKeyCap : 1];
-    uint16_t lb[kFinalKeyCap];
     uint16_t perm[kFinalKeyCap];
-    uint8_t rank[kFinalKeyCap];
     uint16_t smap[kFinalCellCap];
     uint32_t words[kGroupsPerPart];
     uint32_t cnt2[kGroupsPerPart];
@@ -389,7 +448,8 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                                                   uint64_t G, const Triple* __restrict__ Cg, uint32_t T,
                                                   Group* __restrict__ header, Cell* __restrict__ slots,
                                                   uint32_t* __restrict__ ctrl_flags, const int64_t* __restrict__ ctx_off,
-                                                  const uint8_t* __restrict__ ctx_bytes) {
+                                                  const uint8_t* __restrict__ ctx_bytes,
+                                                  const uint8_t* __restrict__ given_t) {
     __shared__ FinalLds<BYTES> L;
     extern __shared__ Triple Cdyn[];   // the T level-two triples
     Triple* const LC = Cdyn;
@@ -398,6 +458,23 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
     const uint32_t nq = (uint32_t)(k1 - k0);
     const uint64_t c0 = cbase[q];
     const uint32_t Sq = (uint32_t)(cbase[q + 1] - c0);
+    const bool fast = nq <= kFinalKeyCap && Sq <= kFinalCellCap;
+    // the partition's records go in flight first; the set-up below overlaps their latency
+    constexpr uint32_t KPT = kFinalKeyCap / kPB;
+    static_assert(kFinalKeyCap % kPB == 0, "whole records per thread");
+    uint64_t xk[KPT];
+    uint32_t vk[KPT], ak[KPT];
+    if (fast) {
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) {
+            const uint32_t i = tid + k * kPB;
+            if (i < nq) {
+                xk[k] = keys[k0 + i];
+                vk[k] = vals[k0 + i];
+                if (BYTES) ak[k] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
+            }
+        }
+    }
     for (uint32_t t = tid; t < T; t += kPB) LC[t] = Cg[t];
     for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) {
         const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
@@ -442,7 +519,6 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             L.gbase[tid] = ps + is - s2;
         }
     }
-    const bool fast = nq <= kFinalKeyCap && Sq <= kFinalCellCap;
     if (fast) {
         // stage the partition's keys; ranks come from a second LDS histogram
         for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
@@ -450,18 +526,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         if (tid < 16) L.mag[tid] = tid ? fastmod_magic(tid * tid) : 0;
         if (tid == 0) L.nbig = 0;
         __syncthreads();
-        constexpr uint32_t KPT = kFinalKeyCap / kPB;
-        uint64_t xk[KPT];
-        uint32_t vk[KPT], ak[KPT];
-#pragma unroll
-        for (uint32_t k = 0; k < KPT; ++k) {
-            const uint32_t i = tid + k * kPB;
-            if (i < nq) {
-                xk[k] = keys[k0 + i];
-                vk[k] = vals[k0 + i];
-                if (BYTES) ak[k] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
-            }
-        }
+        uint32_t lbk[KPT], rk[KPT];
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
@@ -470,9 +535,9 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 L.val[i] = vk[k];
                 if (BYTES) L.aux[i] = ak[k];
                 const uint32_t lb = bucket_of(A, magic, (uint32_t)n, xk[k]) & (kPartBuckets - 1);
-                L.lb[i] = (uint16_t)lb;
+                lbk[k] = lb;
                 const uint32_t sh = 4 * (lb & 7u);
-                L.rank[i] = (uint8_t)((atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u);
+                rk[k] = (atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u;
             }
         }
         __syncthreads();
@@ -482,8 +547,8 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
-                const uint32_t lb = L.lb[i], g = lb >> 3, kk = lb & 7u, w = L.words[g];
-                const uint32_t r = L.rank[i], s = nib(w, kk);
+                const uint32_t lb = lbk[k], g = lb >> 3, kk = lb & 7u, w = L.words[g];
+                const uint32_t r = rk[k], s = nib(w, kk);
                 L.perm[L.gks[g] + prefix_cnt(w, kk) + r] = (uint16_t)i;
                 if (s == 1) L.smap[L.gbase[g] + prefix_sq(w, kk)] = (uint16_t)i;
                 else if (r == 0) L.big[atomicAdd(&L.nbig, 1u)] = (uint16_t)lb;
@@ -499,7 +564,9 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
             const uint64_t M = L.mag[s];
             uint32_t t;
-            if (s <= 8) {
+            if (given_t) {
+                t = given_t[(uint64_t)q * kPartBuckets + b];
+            } else if (s <= 8) {
                 uint64_t kx[8];
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i) kx[i] = i < s ? L.key[L.perm[kst + i]] : 0;
@@ -570,7 +637,8 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             uint32_t t = 0;
             bool exhausted = false;
             if (s >= 2) {
-                t = min_trial(LC, T, s, [&](uint32_t i) { return mine[i]; });
+                t = given_t ? given_t[(uint64_t)q * kPartBuckets + b]
+                            : min_trial(LC, T, s, [&](uint32_t i) { return mine[i]; });
                 exhausted = t == T;
             }
             const uint32_t s2 = s * s;
@@ -673,13 +741,27 @@ static void scan_matrix(const PartArgs& a, uint64_t N, hipStream_t st) {
     hipLaunchKernelGGL(k_xscan_down, nt, kPB, 0, st, a.cnt, N, a.tpre, a.off);
 }
 
+static int scatter_variant() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("FKS_SCATTER_VARIANT");
+        v = (e && e[0] == 'p') ? 1 : 0;
+    }
+    return v;
+}
+
 template <bool AUX>
 static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin, const uint32_t* ain,
                     const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift, uint32_t mask, uint64_t* kout,
                     uint32_t* vout, uint32_t* aout, hipStream_t st) {
-    FKS_TIMED("fks_part_scatter", st,
-              hipLaunchKernelGGL(k_dscatter<AUX>, grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
-                                 shift, mask, a.off, kout, vout, aout));
+    if (scatter_variant() == 1)
+        FKS_TIMED("fks_part_scatter", st,
+                  hipLaunchKernelGGL((k_dscatter_p<AUX, 16>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic,
+                                     ranges, W, shift, mask, a.off, kout, vout, aout));
+    else
+        FKS_TIMED("fks_part_scatter", st,
+                  hipLaunchKernelGGL((k_dscatter<AUX, 16>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic,
+                                     ranges, W, shift, mask, a.off, kout, vout, aout));
 }
 
 // Runs the partition passes of one attempt; stream-ordered outputs: offQ, the
@@ -744,17 +826,18 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
 }
 
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
-                uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, hipStream_t st) {
+                uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
+                hipStream_t st) {
     if (a.bytes)
         FKS_TIMED("fks_part_final", st,
                   hipLaunchKernelGGL(k_pfinal<true>, o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals, o.aux, o.aux_is_pos, a.n,
                                      a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header, slots, flags,
-                                     ctx_off, ctx_bytes));
+                                     ctx_off, ctx_bytes, given_t));
     else
         FKS_TIMED("fks_part_final", st,
                   hipLaunchKernelGGL(k_pfinal<false>, o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals, nullptr, 1, a.n, a.A,
                                      a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header, slots, flags, nullptr,
-                                     nullptr));
+                                     nullptr, given_t));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }

@@ -58,7 +58,9 @@ struct PartOut {
 PartPlan part_plan(uint64_t n);
 uint64_t part_scan_tiles(const PartPlan& P);
 int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o);
+// given_t: trial index of every bucket decided elsewhere (n bytes), or nullptr to search
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
-                uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, hipStream_t st);
+                uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
+                hipStream_t st);
 
 }  // namespace fks

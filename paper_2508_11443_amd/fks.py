@@ -29,7 +29,7 @@ class FksError(RuntimeError):
 
 class fks_params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_uint32), ("T", ctypes.c_uint32), ("R", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("schedule", ctypes.c_uint32)]
 
 
 class fks_prof_entry(ctypes.Structure):
@@ -51,6 +51,7 @@ _VP, _U64, _U32, _I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctype
 SIGNATURES = [
     ("fks_params_default", None, [_VP]),
     ("fks_build_u64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_u64_from_array", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_build_bytes", _I32, [_VP, _VP, _U64, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_lookup_u64", _I32, [_VP, _VP, _U64, _VP, _VP, _U32, _VP]),
     ("fks_contains_u64", _I32, [_VP, _VP, _U64, _VP, _VP]),
@@ -79,6 +80,7 @@ SIGNATURES = [
     ("fks_server_stats", _I32, [_VP, _VP]),
     ("fks_server_map", _VP, [_VP, _U32]),
     ("fks_server_destroy", None, [_VP]),
+    ("fks_probe_random_reads", _I32, [_U64, _U64, _U32, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("fks_prof_enable", _I32, [_I32]),
     ("fks_prof_reset", None, []),
     ("fks_prof_read", _I32, [_VP, _I32]),
@@ -141,9 +143,11 @@ def _u32_types():
     return (torch.int32, torch.uint32)
 
 
-def _params(c=None, T=None, R=None):
+def _params(c=None, T=None, R=None, schedule=None):
     p = fks_params()
     _load().fks_params_default(ctypes.byref(p))
+    if schedule is not None:
+        p.schedule = schedule
     if c is not None:
         p.c = c
     if T is not None:
@@ -181,16 +185,31 @@ class FksMap:
             pass
 
 
-def fks_build_u64(keys, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
-    """from_array_nodup over n uint64 keys (device tensor, int64 or uint64) and uint32 values."""
+def fks_build_u64(keys, vals, seed: int, c=None, T=None, R=None, stream=None, schedule=None) -> FksMap:
+    """from_array_nodup over n uint64 keys (device tensor, int64 or uint64) and uint32 values.
+    schedule=1 searches level two with the paper's flattened rounds (same table)."""
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and values differ in length")
+    p = _params(c, T, R, schedule)
+    out = ctypes.c_void_p()
+    rc = _load().fks_build_u64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
+                               seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
+    _check(rc, "fks_build_u64")
+    return FksMap(out.value, "u64")
+
+
+def fks_build_u64_from_array(keys, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+    """from_array: keys may repeat; a repeated key keeps the value of its first occurrence."""
     n = keys.numel()
     if vals.numel() != n:
         raise ValueError("keys and values differ in length")
     p = _params(c, T, R)
     out = ctypes.c_void_p()
-    rc = _load().fks_build_u64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
-                               seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
-    _check(rc, "fks_build_u64")
+    rc = _load().fks_build_u64_from_array(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
+                                          seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
+                                          ctypes.byref(out))
+    _check(rc, "fks_build_u64_from_array")
     return FksMap(out.value, "u64")
 
 
@@ -464,3 +483,12 @@ class FksServer:
             self.destroy()
         except Exception:
             pass
+
+
+def fks_probe_random_reads(buffer_bytes: int = 2 << 30, probes: int = 1 << 27, width_bytes: int = 16,
+                           stream=None) -> float:
+    """Milliseconds for `probes` random reads of `width_bytes` from a buffer of `buffer_bytes`."""
+    ms = ctypes.c_double()
+    _check(_load().fks_probe_random_reads(buffer_bytes, probes, width_bytes, _stream(stream), ctypes.byref(ms)),
+           "fks_probe_random_reads")
+    return ms.value

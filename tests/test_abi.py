@@ -61,7 +61,7 @@ def test_host_only_entry_points(lib):
     from paper_2508_11443_amd import fks
     p = fks.fks_params()
     lib.fks_params_default(ctypes.byref(p))
-    assert (p.c, p.T, p.R, p.reserved) == (4, 64, 16, 0)
+    assert (p.c, p.T, p.R, p.schedule) == (4, 64, 16, 0)
     assert lib.fks_strerror(0) == b"ok"
     assert lib.fks_strerror(fks.FKS_EDUPKEY).startswith(b"duplicate")
     assert lib.fks_version() >= 10000

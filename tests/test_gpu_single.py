@@ -231,3 +231,63 @@ def test_string_map_edge_cases():
     assert e.value.code == fks.FKS_EINVAL
     e0 = gpu_build_bytes(np.zeros(1, np.int64), np.zeros(0, np.uint8), np.zeros(0, np.uint32), 1)
     assert e0.info()["n"] == 0
+
+
+# ---- from_array: repeated keys ---------------------------------------------------------
+
+@pytest.mark.parametrize("u,distinct", [(1, 1), (10, 3), (5000, 1000), (300000, 100000), (1 << 20, 1 << 16)])
+def test_from_array_bit_exact(u, distinct):
+    """Repeated keys keep the value of their first occurrence; the table equals the oracle's
+    from_array (dedup, then from_array_nodup)."""
+    rng = np.random.default_rng(u)
+    pool = workloads.unique_u64(distinct, u + 3)
+    if distinct > 2:
+        pool[1] = np.uint64(2**64 - 1)       # the all-ones key is handled beside the table
+    keys = pool[rng.integers(0, distinct, size=u)]
+    vals = rng.integers(0, 2**32, size=u, dtype=np.uint64).astype(np.uint32)
+    seed = 99 + u
+    announce(f"gpu from_array: u={u} distinct~{distinct}")
+    m = _fks().fks_build_u64_from_array(to_dev(keys), to_dev(vals), seed)
+    ref = oracle.build_u64_dedup(keys, vals, seed)
+    assert_same_table(m, ref)
+    q, _ = workloads.u64_queries(np.unique(keys), 2000, 0.5, 5)
+    v, f = gpu_lookup(m, q)
+    rv, rf = ref.lookup(q, missing=MISSING)
+    assert (f == rf).all() and (v == rv).all()
+    # first occurrence wins
+    first = {}
+    for k, val in zip(keys.tolist(), vals.tolist()):
+        first.setdefault(k, val)
+    hit = f == 1
+    assert all(first[int(k)] == int(x) for k, x in zip(q[hit], v[hit]))
+
+
+# ---- the paper's flattened rounds as the level-two schedule ------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 9, 1000, 65536, 100003, (1 << 20) + 77])
+def test_rounds_schedule_bit_exact(n):
+    """schedule=1 searches level two with the sortless rounds of Section 2.5 on the GPU; the
+    table must equal the oracle's (and so the per-bucket schedule's) byte for byte."""
+    seed = 0xACE + n
+    announce(f"gpu rounds schedule: n={n} seed={seed}")
+    keys = workloads.unique_u64(n, 3 * n + 1, dense_fraction=0.5)
+    vals = np.arange(n, dtype=np.uint32)
+    m = gpu_build(keys, vals, seed, schedule=1)
+    ref = oracle.build_u64(keys, vals, seed)
+    assert_same_table(m, ref)
+
+
+def test_rounds_schedule_retries_and_duplicates():
+    fks = _fks()
+    announce("gpu rounds schedule: T=1 retries, duplicate keys")
+    keys = workloads.unique_u64(3000, 8)
+    vals = np.arange(3000, dtype=np.uint32)
+    for seed in range(8):
+        m = gpu_build(keys[:40], vals[:40], seed, T=1, R=1024, schedule=1)
+        ref = oracle.build_u64(keys[:40], vals[:40], seed, T=1, R=1024)
+        assert_same_table(m, ref)
+    dup = keys[:1000].copy()
+    dup[10] = dup[500]
+    with pytest.raises(fks.FksError) as e:
+        gpu_build(dup, vals[:1000], 1, schedule=1)
+    assert e.value.code == fks.FKS_EDUPKEY

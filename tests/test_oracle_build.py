@@ -249,3 +249,26 @@ def test_duplicate_strings_are_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.build_bytes(off, data, np.zeros(4, np.uint32), 1)
     assert e.value.code == oracle.EDUPKEY
+
+
+def test_from_array_keeps_first_occurrence():
+    """from_array (Figure 2) over repeated keys: the map holds the distinct keys and each
+    keeps the value of its first occurrence (the reading written down for the paper's
+    unspecified choice); lookups equal a dict built from the first occurrences."""
+    rng = np.random.default_rng(8)
+    pool = workloads.unique_u64(700, 4)
+    keys = pool[rng.integers(0, 700, size=3000)]
+    vals = np.arange(3000, dtype=np.uint32)
+    m = oracle.build_u64_dedup(keys, vals, 5)
+    first = {}
+    for k, v in zip(keys.tolist(), vals.tolist()):
+        first.setdefault(k, v)
+    assert m.n == len(first)
+    q = np.array(list(first.keys()), np.uint64)
+    v, f = m.lookup(q)
+    assert f.all() and [int(x) for x in v] == [first[int(k)] for k in q]
+    # the table equals from_array_nodup over the distinct keys with their kept values
+    ref = oracle.build_u64(q, np.array([first[int(k)] for k in q], np.uint32), 5)
+    h1, s1 = m.export()
+    h2, s2 = ref.export()
+    assert (h1 == h2).all() and (s1 == s2).all()
