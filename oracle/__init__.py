@@ -10,6 +10,9 @@ Modules:
                       of Section 2.2, loaded here through ctypes.
   ``spec``         -- the same fixed readings in pure Python integers, for
                       tiny inputs and for pinning the primitives.
+  ``search_oracle.c`` -- the comparison maps of Section 4: a sorted array with
+                      binary search, and the Eytzinger (level-order) tree of
+                      the same keys, built by the recursive in-order walk.
   ``rounds``       -- the sortless flattened construction of Section 2.5 in
                       numpy, written from the paper's data-parallel vocabulary
                       (Figure 1), to show it picks the same level-two
@@ -17,8 +20,9 @@ Modules:
 """
 from .cbind import (OracleMap, build_u64, build_u64_dedup, build_bytes, liboracle, ensure_built,
                     splitmix, hash32, fingerprint, level1_consts, level2_consts,
-                    batch_seed, OK, EINVAL, ENOMEM, EDUPKEY, EBUILD, OracleError)
+                    batch_seed, search_build, search_lookup, OK, EINVAL, ENOMEM, EDUPKEY, EBUILD,
+                    OracleError)
 
 __all__ = ["OracleMap", "build_u64", "build_u64_dedup", "build_bytes", "liboracle", "ensure_built",
            "splitmix", "hash32", "fingerprint", "level1_consts", "level2_consts",
-           "batch_seed", "OK", "EINVAL", "ENOMEM", "EDUPKEY", "EBUILD", "OracleError"]
+           "batch_seed", "search_build", "search_lookup", "OK", "EINVAL", "ENOMEM", "EDUPKEY", "EBUILD", "OracleError"]

@@ -1,4 +1,5 @@
-"""ctypes binding of the C oracle (``fks_oracle.c``).  Test infrastructure only."""
+"""ctypes binding of the C oracles (``fks_oracle.c``, ``search_oracle.c``).  Test
+infrastructure only."""
 from __future__ import annotations
 
 import ctypes
@@ -8,7 +9,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fks_oracle.c")
+_SRCS = [os.path.join(_HERE, "fks_oracle.c"), os.path.join(_HERE, "search_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, EDUPKEY, EBUILD = 0, -1, -2, -3, -4
@@ -22,16 +23,16 @@ class OracleError(RuntimeError):
 
 
 def compile_oracle() -> str:
-    """Compile the C oracle into ``oracle/liboracle.so`` (gcc, plain -O2)."""
+    """Compile the C oracles into ``oracle/liboracle.so`` (gcc, plain -O2)."""
     tmp = _LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                           "-o", tmp, _SRC])
+                           "-o", tmp] + _SRCS)
     os.replace(tmp, _LIB)
     return _LIB
 
 
 def ensure_built() -> str:
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         compile_oracle()
     return _LIB
 
@@ -72,6 +73,10 @@ def liboracle():
         lib.oracle_free.argtypes = [vp]
         lib.oracle_batch_seed.restype = u64
         lib.oracle_batch_seed.argtypes = [u64, u64]
+        lib.oracle_search_build.restype = i32
+        lib.oracle_search_build.argtypes = [vp, vp, u64, u32, vp, vp]
+        lib.oracle_search_lookup.restype = i32
+        lib.oracle_search_lookup.argtypes = [vp, vp, u64, u32, vp, u64, vp, vp, u32]
         _lib = lib
     return _lib
 
@@ -202,3 +207,27 @@ def build_bytes(offsets: np.ndarray, data: np.ndarray, vals: np.ndarray, sigma: 
     if rc:
         raise OracleError(rc)
     return OracleMap(h.value)
+
+
+def search_build(keys: np.ndarray, vals: np.ndarray, layout: int):
+    """Sorted (layout 0) or Eytzinger (layout 1) arrays of the pairs; raises on
+    duplicate keys."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    vals = np.ascontiguousarray(vals, dtype=np.uint32)
+    ok = np.empty(keys.size, dtype=np.uint64)
+    ov = np.empty(keys.size, dtype=np.uint32)
+    rc = liboracle().oracle_search_build(_ptr(keys), _ptr(vals), keys.size, layout, _ptr(ok), _ptr(ov))
+    if rc != OK:
+        raise OracleError(rc)
+    return ok, ov
+
+
+def search_lookup(lkeys: np.ndarray, lvals: np.ndarray, layout: int, q: np.ndarray, missing: int = 0xFFFFFFFF):
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    vals = np.empty(q.size, dtype=np.uint32)
+    found = np.empty(q.size, dtype=np.uint8)
+    rc = liboracle().oracle_search_lookup(_ptr(lkeys), _ptr(lvals), lkeys.size, layout, _ptr(q), q.size,
+                                          _ptr(vals), _ptr(found), missing)
+    if rc != OK:
+        raise OracleError(rc)
+    return vals, found.astype(bool)
