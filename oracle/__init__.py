@@ -18,11 +18,11 @@ Modules:
                       (Figure 1), to show it picks the same level-two
                       constants as the per-bucket make_2.
 """
-from .cbind import (OracleMap, build_u64, build_u64_dedup, build_bytes, liboracle, ensure_built,
+from .cbind import (OracleMap, build_u64, build_u64_v64, build_u64_dedup, build_bytes, liboracle, ensure_built,
                     splitmix, hash32, fingerprint, level1_consts, level2_consts,
                     batch_seed, search_build, search_lookup, OK, EINVAL, ENOMEM, EDUPKEY, EBUILD,
                     OracleError)
 
-__all__ = ["OracleMap", "build_u64", "build_u64_dedup", "build_bytes", "liboracle", "ensure_built",
+__all__ = ["OracleMap", "build_u64", "build_u64_v64", "build_u64_dedup", "build_bytes", "liboracle", "ensure_built",
            "splitmix", "hash32", "fingerprint", "level1_consts", "level2_consts",
            "batch_seed", "search_build", "search_lookup", "OK", "EINVAL", "ENOMEM", "EDUPKEY", "EBUILD", "OracleError"]

@@ -73,6 +73,10 @@ def liboracle():
         lib.oracle_free.argtypes = [vp]
         lib.oracle_batch_seed.restype = u64
         lib.oracle_batch_seed.argtypes = [u64, u64]
+        lib.oracle_build_u64_v64.restype = i32
+        lib.oracle_build_u64_v64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+        lib.oracle_lookup_u64_v64.restype = i32
+        lib.oracle_lookup_u64_v64.argtypes = [vp, vp, u64, vp, vp, u64]
         lib.oracle_search_build.restype = i32
         lib.oracle_search_build.argtypes = [vp, vp, u64, u32, vp, vp]
         lib.oracle_search_lookup.restype = i32
@@ -127,7 +131,7 @@ class OracleMap:
         liboracle().oracle_info(self._h, _ptr(info))
         self.info = {k: int(v) for k, v in zip(INFO_FIELDS, info)}
         self.n, self.S, self.r = self.info["n"], self.info["S"], self.info["r"]
-        self.kind = "u64" if self.info["kind"] == 0 else "bytes"
+        self.kind = {0: "u64", 1: "bytes", 2: "u64v64"}[self.info["kind"]]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -148,6 +152,15 @@ class OracleMap:
         vals = np.zeros(q.size, np.uint32)
         found = np.zeros(q.size, np.uint8)
         rc = liboracle().oracle_lookup_u64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
+        if rc:
+            raise OracleError(rc)
+        return vals, found
+
+    def lookup_v64(self, queries: np.ndarray, missing: int = 2**64 - 1):
+        q = np.ascontiguousarray(queries, np.uint64)
+        vals = np.zeros(q.size, np.uint64)
+        found = np.zeros(q.size, np.uint8)
+        rc = liboracle().oracle_lookup_u64_v64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
         if rc:
             raise OracleError(rc)
         return vals, found
@@ -174,6 +187,19 @@ def build_u64(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int
     assert k.size == v.size
     h = ctypes.c_void_p()
     rc = liboracle().oracle_build_u64(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
+    if rc:
+        raise OracleError(rc)
+    return OracleMap(h.value)
+
+
+def build_u64_v64(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int = 64,
+                  R: int = 16) -> OracleMap:
+    """64-bit values: the value's high half sits in the cell's aux word."""
+    k = np.ascontiguousarray(keys, np.uint64)
+    v = np.ascontiguousarray(vals, np.uint64)
+    assert k.size == v.size
+    h = ctypes.c_void_p()
+    rc = liboracle().oracle_build_u64_v64(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
     if rc:
         raise OracleError(rc)
     return OracleMap(h.value)

@@ -58,7 +58,7 @@
 #define OR_P61 ((1ULL << 61) - 1ULL)
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_EDUPKEY = -3, OR_EBUILD = -4 };
-enum { OR_KIND_U64 = 0, OR_KIND_BYTES = 1 };
+enum { OR_KIND_U64 = 0, OR_KIND_BYTES = 1, OR_KIND_U64V64 = 2 };
 
 /* ---- R1: SplitMix64 ---------------------------------------------------- */
 
@@ -162,7 +162,7 @@ static int or_bytes_equal(const oracle_map* M, const int64_t* off, const uint8_t
  *   keyv[i]: the integer the construction hashes (the key itself, or the
  *            string fingerprint under this attempt's beta).
  */
-static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
+static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals, const uint32_t* vals_hi,
                       const int64_t* off, const uint8_t* bytes, uint32_t r)
 {
     uint64_t n = M->n;
@@ -246,7 +246,7 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
             for (uint64_t q1 = gstart[j]; q1 < gstart[j + 1]; ++q1)
                 for (uint64_t q2 = q1 + 1; q2 < gstart[j + 1]; ++q2) {
                     uint64_t i1 = members[q1], i2 = members[q2];
-                    if (M->kind == OR_KIND_U64) {
+                    if (M->kind != OR_KIND_BYTES) {
                         if (keyv[i1] == keyv[i2]) dup = 1;
                     } else if (or_bytes_equal(M, off, bytes, i1, i2)) {
                         dup = 1;
@@ -294,7 +294,8 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
         uint8_t* cell = slots + 16 * p;
         or_put_u64(cell, keyv[i]);
         or_put_u32(cell + 8, vals[i]);
-        or_put_u32(cell + 12, M->kind == OR_KIND_BYTES ? (uint32_t)i : 0u);
+        /* aux: the key index of a string key, the high half of a 64-bit value */
+        or_put_u32(cell + 12, M->kind == OR_KIND_BYTES ? (uint32_t)i : (vals_hi ? vals_hi[i] : 0u));
         occupied[p] = 1;
     }
     /* empty cells copy the lowest occupied cell of the same bucket */
@@ -369,12 +370,46 @@ int oracle_build_u64(const uint64_t* keys, const uint32_t* vals, uint64_t n, uin
         return OR_OK;
     }
     for (uint32_t r = 0; r < R; ++r) {
-        rc = or_attempt(M, keys, vals, NULL, NULL, r);
+        rc = or_attempt(M, keys, vals, NULL, NULL, NULL, r);
         if (rc == OR_OK) { *out = M; return OR_OK; }
         if (rc < 0) { oracle_free(M); return rc; }
     }
     oracle_free(M);
     return OR_EBUILD;
+}
+
+/* 64-bit values (the paper's value type is polymorphic, Figure 2): the same
+ * construction over the keys; a cell holds the value's low half where a 32-bit
+ * map holds its value and the high half in its aux word. */
+int oracle_build_u64_v64(const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t sigma,
+                         uint32_t c, uint32_t T, uint32_t R, oracle_map** out)
+{
+    int rc = or_check_params(n, c, T, R);
+    if (rc) return rc;
+    oracle_map* M = or_new(OR_KIND_U64V64, n, sigma, c, T, R);
+    if (!M) return OR_ENOMEM;
+    if (n == 0) {
+        rc = or_empty_map(M);
+        if (rc) { oracle_free(M); return rc; }
+        *out = M;
+        return OR_OK;
+    }
+    uint32_t* lo = malloc(sizeof(uint32_t) * n);
+    uint32_t* hi = malloc(sizeof(uint32_t) * n);
+    if (!lo || !hi) { free(lo); free(hi); oracle_free(M); return OR_ENOMEM; }
+    for (uint64_t i = 0; i < n; ++i) {
+        lo[i] = (uint32_t)vals[i];
+        hi[i] = (uint32_t)(vals[i] >> 32);
+    }
+    for (uint32_t r = 0; r < R; ++r) {
+        rc = or_attempt(M, keys, lo, hi, NULL, NULL, r);
+        if (rc == OR_OK) break;
+        if (rc < 0) break;
+    }
+    free(lo); free(hi);
+    if (rc == OR_OK) { *out = M; return OR_OK; }
+    oracle_free(M);
+    return rc < 0 ? rc : OR_EBUILD;
 }
 
 int oracle_build_bytes(const int64_t* offsets, const uint8_t* bytes, const uint32_t* vals,
@@ -410,7 +445,7 @@ int oracle_build_bytes(const int64_t* offsets, const uint8_t* bytes, const uint3
         for (uint64_t i = 0; i < n; ++i)
             y[i] = oracle_fingerprint(M->ctx_bytes + M->ctx_off[i],
                                       (uint64_t)(M->ctx_off[i + 1] - M->ctx_off[i]), c1[3]);
-        rc = or_attempt(M, y, vals, M->ctx_off, M->ctx_bytes, r);
+        rc = or_attempt(M, y, vals, NULL, M->ctx_off, M->ctx_bytes, r);
         if (rc == OR_OK) { free(y); *out = M; return OR_OK; }
         if (rc < 0) { free(y); oracle_free(M); return rc; }
     }
@@ -489,6 +524,20 @@ int oracle_lookup_u64(const oracle_map* M, const uint64_t* q, uint64_t m,
         int hit = p >= 0 && or_get_u64(M->slots + 16 * (uint64_t)p) == q[i];
         found[i] = (uint8_t)hit;
         vals[i] = hit ? or_get_u32(M->slots + 16 * (uint64_t)p + 8) : missing;
+    }
+    return OR_OK;
+}
+
+int oracle_lookup_u64_v64(const oracle_map* M, const uint64_t* q, uint64_t m,
+                          uint64_t* vals, uint8_t* found, uint64_t missing)
+{
+    if (M->kind != OR_KIND_U64V64) return OR_EINVAL;
+    for (uint64_t i = 0; i < m; ++i) {
+        int64_t p = or_probe(M, q[i]);
+        const uint8_t* cell = M->slots + 16 * (uint64_t)(p >= 0 ? p : 0);
+        int hit = p >= 0 && or_get_u64(cell) == q[i];
+        found[i] = (uint8_t)hit;
+        vals[i] = hit ? ((uint64_t)or_get_u32(cell + 12) << 32) | or_get_u32(cell + 8) : missing;
     }
     return OR_OK;
 }

@@ -272,3 +272,32 @@ def test_from_array_keeps_first_occurrence():
     h1, s1 = m.export()
     h2, s2 = ref.export()
     assert (h1 == h2).all() and (s1 == s2).all()
+
+
+@pytest.mark.parametrize("n", [0, 1, 9, 1000, 20000])
+def test_u64_values(n):
+    """64-bit values (the value type is polymorphic, Figure 2): lookups equal a dict
+    of the full 64-bit values, and the table is the 32-bit map's table over the low
+    halves with the high halves in the aux words (the construction never reads the
+    values)."""
+    rng = np.random.default_rng(n + 3)
+    keys = workloads.unique_u64(n, n + 11)
+    vals = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+    m = oracle.build_u64_v64(keys, vals, 77)
+    assert m.kind == "u64v64"
+    q, expect = workloads.u64_queries(keys, max(2 * n, 100), 0.5, 5)
+    v, f = m.lookup_v64(q, missing=12345)
+    d = dict(zip(keys.tolist(), vals.tolist()))
+    assert [bool(x) for x in f] == [int(x) in d for x in q]
+    assert [int(x) for x in v] == [d.get(int(x), 12345) for x in q]
+    ref = oracle.build_u64(keys, (vals & np.uint64(0xFFFFFFFF)).astype(np.uint32), 77)
+    h1, s1 = m.export()
+    h2, s2 = ref.export()
+    assert (h1 == h2).all()
+    c1, c2 = s1.reshape(-1, 16), s2.reshape(-1, 16)
+    assert (c1[:, :12] == c2[:, :12]).all()
+    hi = c1[:, 12:16].copy().view(np.uint32).ravel()
+    cell_keys = c1[:, :8].copy().view(np.uint64).ravel()
+    assert [int(h) for h in hi] == [d[int(k)] >> 32 for k in cell_keys]
+    with pytest.raises(oracle.OracleError):
+        m.lookup(q)   # a 64-bit-value map answers 64-bit lookups only
