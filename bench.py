@@ -45,13 +45,6 @@ KERNEL_SRC = {
     "fks_lookup_u64": "paper_2508_11443_amd/csrc/lookup.hip",
     "fks_contains_u64": "paper_2508_11443_amd/csrc/lookup.hip",
     "fks_lookup_bytes": "paper_2508_11443_amd/csrc/lookup.hip",
-    "fks_hist": "paper_2508_11443_amd/csrc/build.hip",
-    "fks_group": "paper_2508_11443_amd/csrc/build.hip",
-    "fks_search_write": "paper_2508_11443_amd/csrc/build.hip",
-    "fks_scan_reduce": "paper_2508_11443_amd/csrc/build.hip",
-    "fks_scan_down": "paper_2508_11443_amd/csrc/build.hip",
-    "fks_scan_tiles": "paper_2508_11443_amd/csrc/build.hip",
-    "fks_zero_counts": "paper_2508_11443_amd/csrc/build.hip",
     "fks_part_count": "paper_2508_11443_amd/csrc/partition.hip",
     "fks_part_scatter": "paper_2508_11443_amd/csrc/partition.hip",
     "fks_part_sizes": "paper_2508_11443_amd/csrc/partition.hip",
@@ -69,18 +62,6 @@ def algorithmic_bytes(kernel, n, m, S, hit_frac, nonempty_frac):
     if kernel == "fks_contains_u64":
         probes2 = hit_frac + (1 - hit_frac) * nonempty_frac
         return m * (8 + 16 + 16 * probes2 + 1)
-    if kernel == "fks_hist":
-        return n * (8 + 1) + G * 4 * 2
-    if kernel == "fks_group":
-        return n * (8 + 4 + 1 + 16) + G * (4 + 8)
-    if kernel == "fks_search_write":
-        return n * 16 + G * (4 + 8 + 16) + S * 16
-    if kernel in ("fks_scan_reduce",):
-        return G * 4
-    if kernel == "fks_scan_down":
-        return G * (4 + 8)
-    if kernel == "fks_zero_counts":
-        return G * 4
     if kernel == "fks_part_count":          # one counting pass: the keys
         return n * 8
     if kernel == "fks_part_scatter":        # one scatter pass: keys and values in and out
@@ -149,6 +130,27 @@ def _median_ms(fn, reps, stream):
         if hasattr(r, "destroy"):
             r.destroy()
     return float(np.median(out))
+
+
+def extra_search(d_keys, d_vals, d_q, d_expect, d_v, d_f, stream, hash_build_ms, hash_lookup_ms, reps=3):
+    """The comparison maps of Section 4 on the same 2^26 keys and needles: radix-sorted
+    array with binary search, and the Eytzinger layout with its descent."""
+    import torch
+    from paper_2508_11443_amd import fks
+    n, m = d_keys.numel(), d_q.numel()
+    res = {}
+    for layout, name in ((fks.FKS_LAYOUT_SORTED, "sorted_binary_search"), (fks.FKS_LAYOUT_EYTZINGER, "eytzinger")):
+        fks.fks_sorted_build_u64(d_keys, d_vals, layout, stream=stream).destroy()
+        tb = _median_ms(lambda: fks.fks_sorted_build_u64(d_keys, d_vals, layout, stream=stream), reps, stream)
+        s = fks.fks_sorted_build_u64(d_keys, d_vals, layout, stream=stream)
+        tl = _median_ms(lambda: fks.fks_sorted_lookup_u64(s, d_q, d_v, d_f, stream=stream), reps, stream)
+        ok = bool(torch.equal(d_f, d_expect)) and bool((d_v[~d_expect.bool()] == -1).all())
+        s.destroy()
+        res[name] = {"build_ms": round(tb, 4), "lookup_ms": round(tl, 4),
+                     "build_mkeys_per_s": round(n / tb / 1e3, 1), "lookup_mq_per_s": round(m / tl / 1e3, 1),
+                     "hash_build_speedup": round(tb / hash_build_ms, 2),
+                     "hash_lookup_speedup": round(tl / hash_lookup_ms, 2), "answers_checked": ok}
+    return res
 
 
 def extra_strings(dev, reps=5):
@@ -437,6 +439,8 @@ def main():
         out["rounds_schedule"] = {"build_ms": round(tr, 4), "per_bucket_build_ms": round(build_ms, 4),
                                   "slowdown": round(tr / build_ms, 2),
                                   "same_header_bytes": bool((hr == hb).all())}
+        log("extra: comparison maps (sorted array, Eytzinger)")
+        out["search_maps"] = extra_search(d_keys, d_vals, d_q, d_expect, d_v, d_f, stream, build_ms, lookup_ms)
         del d_keys, d_vals, d_q, d_expect, d_v, d_f
         torch.cuda.empty_cache()
         log("extra: strings")

@@ -87,7 +87,7 @@ typedef struct fks_map_info {
     uint64_t ctx_bytes;   /* bytes of the copied string context (0 for integer keys) */
     uint64_t seed;        /* sigma */
     uint32_t r;           /* accepted level-one attempt */
-    uint32_t kind;        /* 0 = uint64 keys, 1 = byte-string keys */
+    uint32_t kind;        /* 0 = uint64 keys, 1 = byte-string keys, 2 = uint64 keys with uint64 values */
     uint32_t c, T, R;
     uint32_t max_t;       /* largest trial index used by any bucket */
     uint64_t device_bytes;/* device memory the map holds */
@@ -124,6 +124,18 @@ int fks_build_u64_from_array(const uint64_t* d_keys, const uint32_t* d_vals, uin
                              const fks_params* params, void* stream, fks_map** out);
 
 /*
+ * from_array_nodup for 64-bit keys with 64-bit values (the value type of
+ * Figure 2 is polymorphic).  The construction and the header are those of
+ * fks_build_u64 over the same keys; a cell keeps the value's low half where a
+ * 32-bit map keeps its value and the high half in its aux word, so the table
+ * takes no more memory.  d_vals: n uint64 values (device).  Answer lookups
+ * with fks_lookup_u64_v64 (fks_contains_u64 also works; fks_lookup_u64 returns
+ * FKS_EINVAL).  Errors: as fks_build_u64.
+ */
+int fks_build_u64_v64(const uint64_t* d_keys, const uint64_t* d_vals, uint64_t n, uint64_t seed,
+                      const fks_params* params, void* stream, fks_map** out);
+
+/*
  * from_array_nodup for byte-string keys (Section 3.1 contexts, Section 3.3.1
  * slices).  Key i is bytes [d_offsets[i], d_offsets[i+1]) of d_bytes (CSR;
  * a string may be empty).  Offsets must be non-decreasing, d_offsets[0] >= 0
@@ -148,9 +160,16 @@ int fks_build_bytes(const int64_t* d_offsets, const uint8_t* d_bytes, uint64_t n
 int fks_lookup_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m,
                    uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, void* stream);
 
-/* Membership only (Section 4): d_found_out[i] = 1 iff d_queries[i] is a key. */
+/* Membership only (Section 4): d_found_out[i] = 1 iff d_queries[i] is a key
+   (maps of kind 0 or 2). */
 int fks_contains_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m,
                      uint8_t* d_found_out, void* stream);
+
+/* lookup on a map built by fks_build_u64_v64: d_vals_out (required) receives
+   the 64-bit value or `missing`; d_found_out may be NULL.  Errors: FKS_EINVAL
+   (other map kinds, NULL arguments with m > 0), FKS_EHIP. */
+int fks_lookup_u64_v64(const fks_map* map, const uint64_t* d_queries, uint64_t m, uint64_t* d_vals_out,
+                       uint8_t* d_found_out, uint64_t missing, void* stream);
 
 /*
  * lookup for m string needles given in their own context (Section 3.1: the
@@ -295,6 +314,31 @@ void fks_server_destroy(fks_server* srv);
  * probes / time is the ceiling that one- and two-probe lookups run against. */
 int fks_probe_random_reads(uint64_t buffer_bytes, uint64_t probes, uint32_t width_bytes, void* stream,
                            double* ms_out);
+
+/* ---- comparison maps: sorted array and Eytzinger order (Section 4) --------
+ * The search structures the paper measures its hash maps against: the pairs
+ * sorted by key and found by binary search, or the same sorted pairs stored in
+ * the level order of the complete binary search tree (Eytzinger layout) and
+ * found by a root-to-leaf descent.  Same contract as fks_build_u64: keys
+ * distinct (FKS_EDUPKEY otherwise), lookups return the value of the equal key
+ * or `missing`.                                                              */
+typedef struct fks_sorted fks_sorted;
+#define FKS_LAYOUT_SORTED 0u      /* ascending keys, binary search */
+#define FKS_LAYOUT_EYTZINGER 1u   /* level order of the complete search tree */
+
+/* d_keys, d_vals: n device records, read only during the call; n < 2^32.
+   The structure owns 12 bytes of device memory per key.  Synchronizes the
+   stream once (duplicate check).  Errors: FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY,
+   FKS_EHIP. */
+int fks_sorted_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint32_t layout,
+                         void* stream, fks_sorted** out);
+/* As fks_lookup_u64: d_vals_out may be NULL (membership only); asynchronous. */
+int fks_sorted_lookup_u64(const fks_sorted* s, const uint64_t* d_queries, uint64_t m, uint32_t* d_vals_out,
+                          uint8_t* d_found_out, uint32_t missing_value, void* stream);
+/* Copies the n keys and values in layout order to host arrays. */
+int fks_sorted_export(const fks_sorted* s, uint64_t* h_keys, uint32_t* h_vals);
+int fks_sorted_info(const fks_sorted* s, uint64_t* n, uint32_t* layout);
+void fks_sorted_destroy(fks_sorted* s);
 
 /* ---- kernel timing ------------------------------------------------------
  * When enabled, every kernel the library launches is bracketed by two HIP

@@ -9,6 +9,11 @@ a hash of the kernel's source file, so that ``bench.py`` reports the traffic onl
 kernel is unchanged.
 
     python -m paper_2508_11443_amd.counters FETCH.csv WRITE.csv profiles/traffic.json
+
+A kernel-trace run (``rocprofv3 --kernel-trace --stats --output-format csv``) is turned
+into a markdown table of per-kernel dispatch durations and resources with
+
+    python -m paper_2508_11443_amd.counters trace KERNEL_TRACE.csv
 """
 from __future__ import annotations
 
@@ -74,7 +79,39 @@ def summarize(fetch_csv: str, write_csv: str):
     return out
 
 
+def _short(name: str) -> str:
+    name = name.split("(")[0]
+    return name.replace("void ", "").replace("fks::", "").replace(" ", "")
+
+
+def trace_table(trace_csv: str) -> str:
+    """Per library kernel: dispatches, average / min / max duration (us), registers, LDS,
+    scratch."""
+    rows = _rows(trace_csv)
+    by = {}
+    for r in rows:
+        if "fks::" not in r["Kernel_Name"]:
+            continue   # the harness's own torch kernels
+        name = _short(r["Kernel_Name"])
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        ent = by.setdefault(name, {"d": [], "vgpr": r.get("Arch_VGPR_Count", r.get("VGPR_Count", "")),
+                                   "sgpr": r.get("SGPR_Count", ""), "lds": r.get("LDS_Block_Size", ""),
+                                   "scratch": r.get("Scratch_Size", ""),
+                                   "grid": r.get("Grid_Size", r.get("Grid_Size_X", ""))})
+        ent["d"].append(us)
+    lines = ["| kernel | calls | avg us | min us | max us | grid | VGPR | SGPR | LDS B | scratch B |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for name, e in sorted(by.items(), key=lambda kv: -sum(kv[1]["d"])):
+        d = e["d"]
+        lines.append(f"| {name} | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} | {e['grid']} | "
+                     f"{e['vgpr']} | {e['sgpr']} | {e['lds']} | {e['scratch']} |")
+    return "\n".join(lines)
+
+
 def main(argv):
+    if len(argv) >= 3 and argv[1] == "trace":
+        print(trace_table(argv[2]))
+        return
     fetch_csv, write_csv, dest = argv[1:4]
     data = summarize(fetch_csv, write_csv)
     with open(dest, "w") as f:

@@ -17,23 +17,27 @@ namespace fks {
 constexpr int kLBlock = 256;
 constexpr int kQ = 4;   // needles in flight per thread
 
-__global__ void k_fill_outputs(uint64_t m, uint32_t* __restrict__ vals, uint8_t* __restrict__ found,
-                               uint32_t missing) {
+__global__ void k_fill_outputs(uint64_t m, uint32_t* __restrict__ vals, uint64_t* __restrict__ vals64,
+                               uint8_t* __restrict__ found, uint32_t missing, uint64_t missing64) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (uint64_t)gridDim.x * blockDim.x) {
         if (vals) vals[i] = missing;
+        if (vals64) vals64[i] = missing64;
         if (found) found[i] = 0;
     }
 }
 
-template <bool WANT_VALS, bool WANT_FOUND>
+// V64: 64-bit values, the high half in the cell's aux word
+template <bool WANT_VALS, bool WANT_FOUND, bool V64 = false>
 __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict__ header,
                                                           const Cell* __restrict__ slots, Triple A,
                                                           uint64_t magic, uint32_t n,
                                                           const Triple* __restrict__ Cg, uint32_t T,
                                                           const uint64_t* __restrict__ q, uint64_t m,
                                                           uint32_t* __restrict__ vals,
-                                                          uint8_t* __restrict__ found, uint32_t missing) {
+                                                          uint8_t* __restrict__ found, uint32_t missing,
+                                                          uint64_t* __restrict__ vals64 = nullptr,
+                                                          uint64_t missing64 = 0) {
     __shared__ Triple C[kTMax];
     for (uint32_t t = threadIdx.x; t < T; t += kLBlock) C[t] = Cg[t];
     __syncthreads();
@@ -74,7 +78,8 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
             const uint64_t i = base + threadIdx.x + (uint64_t)k * kLBlock;
             if (i < m) {
                 const bool hit = s[k] && c[k].key == x[k];
-                if (WANT_VALS) vals[i] = hit ? c[k].val : missing;
+                if (WANT_VALS && V64) vals64[i] = hit ? ((uint64_t)c[k].aux << 32) | c[k].val : missing64;
+                if (WANT_VALS && !V64) vals[i] = hit ? c[k].val : missing;
                 if (WANT_FOUND) found[i] = hit ? 1 : 0;
             }
         }
@@ -156,12 +161,14 @@ using namespace fks;
 
 extern "C" int fks_lookup_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m, uint32_t* d_vals_out,
                               uint8_t* d_found_out, uint32_t missing, void* stream) {
-    if (!map || map->kind != 0 || (m && !d_queries)) return FKS_EINVAL;
+    // 32-bit values from a map with 32-bit values; membership from any integer-key map
+    if (!map || (m && !d_queries)) return FKS_EINVAL;
+    if (map->kind != 0 && !(map->kind == 2 && !d_vals_out)) return FKS_EINVAL;
     if (m == 0 || (!d_vals_out && !d_found_out)) return FKS_OK;
     hipStream_t st = (hipStream_t)stream;
     if (map->n == 0) {
-        FKS_TIMED("fks_fill_outputs", st, hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, d_vals_out, d_found_out,
-                           missing));
+        FKS_TIMED("fks_fill_outputs", st, hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, d_vals_out, nullptr, d_found_out,
+                           missing, 0ull));
     } else {
         const unsigned grid = lookup_grid(m, (uint64_t)kLBlock * kQ);
         if (d_vals_out && d_found_out)
@@ -187,14 +194,40 @@ extern "C" int fks_contains_u64(const fks_map* map, const uint64_t* d_queries, u
     return fks_lookup_u64(map, d_queries, m, nullptr, d_found_out, 0, stream);
 }
 
+extern "C" int fks_lookup_u64_v64(const fks_map* map, const uint64_t* d_queries, uint64_t m, uint64_t* d_vals_out,
+                                  uint8_t* d_found_out, uint64_t missing, void* stream) {
+    if (!map || map->kind != 2 || (m && (!d_queries || !d_vals_out))) return FKS_EINVAL;
+    if (m == 0) return FKS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (map->n == 0) {
+        FKS_TIMED("fks_fill_outputs", st,
+                  hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, nullptr, d_vals_out,
+                                     d_found_out, 0u, missing));
+    } else {
+        const unsigned grid = lookup_grid(m, (uint64_t)kLBlock * kQ);
+        if (d_found_out)
+            FKS_TIMED("fks_lookup_u64_v64", st,
+                      hipLaunchKernelGGL((k_lookup_u64<true, true, true>), grid, kLBlock, 0, st, map->header,
+                                         map->slots, map->A, map->magic_n, (uint32_t)map->n, map->C, map->T,
+                                         d_queries, m, nullptr, d_found_out, 0u, d_vals_out, missing));
+        else
+            FKS_TIMED("fks_lookup_u64_v64", st,
+                      hipLaunchKernelGGL((k_lookup_u64<true, false, true>), grid, kLBlock, 0, st, map->header,
+                                         map->slots, map->A, map->magic_n, (uint32_t)map->n, map->C, map->T,
+                                         d_queries, m, nullptr, nullptr, 0u, d_vals_out, missing));
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
 static int lookup_bytes_impl(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes, uint64_t m,
                              uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, void* stream) {
     if (!map || map->kind != 1 || (m && (!d_q_offsets || !d_q_bytes))) return FKS_EINVAL;
     if (m == 0 || (!d_vals_out && !d_found_out)) return FKS_OK;
     hipStream_t st = (hipStream_t)stream;
     if (map->n == 0) {
-        FKS_TIMED("fks_fill_outputs", st, hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, d_vals_out, d_found_out,
-                           missing));
+        FKS_TIMED("fks_fill_outputs", st, hipLaunchKernelGGL(k_fill_outputs, lookup_grid(m, kLBlock), kLBlock, 0, st, m, d_vals_out, nullptr, d_found_out,
+                           missing, 0ull));
     } else {
         const unsigned grid = lookup_grid(m, (uint64_t)kLBlock * 2);
         if (d_vals_out)

@@ -16,7 +16,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdlib>
 
 #include "fks_internal.hpp"
 #include "partition.hpp"
@@ -134,16 +133,24 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
     worker_range(ranges, n, W, a, b);
     const uint32_t tid = threadIdx.x;
     run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
-    for (uint64_t ts = a; ts < b; ts += (kPB * ITEMS)) {
-        tcnt[tid] = 0;
-        __syncthreads();
-        uint64_t x[ITEMS];
-        uint32_t bin[ITEMS], rank[ITEMS];
+    // a tile's records are loaded into registers one tile ahead: the loads of
+    // tile i+1 are in flight while tile i is written out
+    uint64_t x[ITEMS];
+    uint32_t v[ITEMS], u[AUX ? ITEMS : 1];
+    auto load = [&](uint64_t ts) {
 #pragma unroll
         for (uint32_t k = 0; k < ITEMS; ++k) {
             const uint64_t i = ts + tid + (uint64_t)k * kPB;
             x[k] = i < b ? keys[i] : 0;
+            v[k] = i < b ? vals[i] : 0;
+            if (AUX) u[AUX ? k : 0] = i < b ? (aux ? aux[i] : (uint32_t)i) : 0;
         }
+    };
+    if (a < b) load(a);
+    for (uint64_t ts = a; ts < b; ts += (kPB * ITEMS)) {
+        tcnt[tid] = 0;
+        __syncthreads();
+        uint32_t bin[ITEMS], rank[ITEMS];
 #pragma unroll
         for (uint32_t k = 0; k < ITEMS; ++k) {
             const uint64_t i = ts + tid + (uint64_t)k * kPB;
@@ -162,11 +169,12 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
             if (i < b) {
                 const uint32_t e = toff[bin[k]] + rank[k];
                 skey[e] = x[k];
-                sval[e] = vals[i];
-                if (AUX) saux[e] = aux ? aux[i] : (uint32_t)i;
+                sval[e] = v[k];
+                if (AUX) saux[e] = u[AUX ? k : 0];
                 sbin[e] = (uint8_t)bin[k];
             }
         }
+        if (ts + (kPB * ITEMS) < b) load(ts + (kPB * ITEMS));
         __syncthreads();
         const uint32_t cnt = (uint32_t)min((uint64_t)(kPB * ITEMS), b - ts);
         for (uint32_t e = tid; e < cnt; e += kPB) {
@@ -175,66 +183,6 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
             keys_out[dest] = skey[e];
             vals_out[dest] = sval[e];
             if (AUX) aux_out[dest] = saux[e];
-        }
-        __syncthreads();
-        run[tid] += tcnt[tid];
-    }
-}
-
-// Same scatter, staging only each slot's source position within the tile (the
-// records are read again, from L2, when the runs are written): a small LDS
-// footprint, so more workgroups per CU.
-template <bool AUX, uint32_t ITEMS>
-__global__ __launch_bounds__(kPB) void k_dscatter_p(const uint64_t* __restrict__ keys,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const uint32_t* __restrict__ aux, uint64_t n, Triple A,
-                                                      uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
-                                                      uint32_t shift, uint32_t mask, const uint32_t* __restrict__ off,
-                                                      uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-                                                      uint32_t* __restrict__ aux_out) {
-    constexpr uint32_t TILE = kPB * ITEMS;
-    __shared__ uint16_t ssrc[TILE];
-    __shared__ uint8_t sbin[TILE];
-    __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
-    __shared__ uint32_t wsum[kPB / 64];
-    uint64_t a, b;
-    worker_range(ranges, n, W, a, b);
-    const uint32_t tid = threadIdx.x;
-    run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
-    for (uint64_t ts = a; ts < b; ts += TILE) {
-        tcnt[tid] = 0;
-        __syncthreads();
-        uint32_t bin[ITEMS], rank[ITEMS];
-#pragma unroll
-        for (uint32_t k = 0; k < ITEMS; ++k) {
-            const uint64_t i = ts + tid + (uint64_t)k * kPB;
-            if (i < b) {
-                const uint32_t q = bucket_of(A, magic, (uint32_t)n, keys[i]) >> kPartBits;
-                bin[k] = (q >> shift) & mask;
-                rank[k] = atomicAdd(&tcnt[bin[k]], 1u);
-            }
-        }
-        __syncthreads();
-        toff[tid] = block_exscan256(tcnt[tid], wsum);
-        __syncthreads();
-#pragma unroll
-        for (uint32_t k = 0; k < ITEMS; ++k) {
-            const uint64_t i = ts + tid + (uint64_t)k * kPB;
-            if (i < b) {
-                const uint32_t e = toff[bin[k]] + rank[k];
-                ssrc[e] = (uint16_t)(tid + k * kPB);
-                sbin[e] = (uint8_t)bin[k];
-            }
-        }
-        __syncthreads();
-        const uint32_t cnt = (uint32_t)min((uint64_t)TILE, b - ts);
-        for (uint32_t e = tid; e < cnt; e += kPB) {
-            const uint32_t bb = sbin[e];
-            const uint64_t src = ts + ssrc[e];
-            const uint64_t dest = (uint64_t)run[bb] + (e - toff[bb]);
-            keys_out[dest] = keys[src];
-            vals_out[dest] = vals[src];
-            if (AUX) aux_out[dest] = aux ? aux[src] : (uint32_t)src;
         }
         __syncthreads();
         run[tid] += tcnt[tid];
@@ -335,12 +283,24 @@ __global__ __launch_bounds__(kPB) void k_psizes(const uint64_t* __restrict__ key
     __syncthreads();
     const uint64_t lo = offQ[q], hi = offQ[q + 1];
     bool over = false;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kPB) {
-        const uint32_t lb = bucket_of(A, magic, (uint32_t)n, keys[i]) & (kPartBuckets - 1);
+    auto count = [&](uint64_t x) {
+        const uint32_t lb = bucket_of(A, magic, (uint32_t)n, x) & (kPartBuckets - 1);
         const uint32_t sh = 4 * (lb & 7u);
         const uint32_t old = atomicAdd(&words[lb >> 3], 1u << sh);
         over |= ((old >> sh) & 15u) == 15u;
+    };
+    // a typical partition's keys are all loaded before the first is hashed
+    constexpr uint32_t KPT = 5;
+    uint64_t x[KPT];
+#pragma unroll
+    for (uint32_t k = 0; k < KPT; ++k) {
+        const uint64_t i = lo + threadIdx.x + (uint64_t)k * kPB;
+        x[k] = i < hi ? keys[i] : 0;
     }
+#pragma unroll
+    for (uint32_t k = 0; k < KPT; ++k)
+        if (lo + threadIdx.x + (uint64_t)k * kPB < hi) count(x[k]);
+    for (uint64_t i = lo + threadIdx.x + (uint64_t)KPT * kPB; i < hi; i += kPB) count(keys[i]);
     if (over) atomicOr(oversize, 1u);
     __syncthreads();
     uint32_t sq = 0;
@@ -377,9 +337,10 @@ __device__ __forceinline__ bool test_set4(uint64_t& m0, uint64_t& m1, uint64_t& 
 }
 
 template <typename KeyAt>
-__device__ __forceinline__ uint32_t min_trial(const Triple* C, uint32_t T, uint32_t s, KeyAt key_at) {
+__device__ __forceinline__ uint32_t min_trial(const Triple* C, uint32_t T, uint32_t s, KeyAt key_at,
+                                              uint32_t t0 = 0) {
     const uint32_t s2 = s * s;
-    for (uint32_t t = 0; t < T; ++t) {
+    for (uint32_t t = t0; t < T; ++t) {
         const Triple c = C[t];
         uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
         bool collide = false;
@@ -399,11 +360,11 @@ __device__ __forceinline__ bool same_string(const int64_t* off, const uint8_t* b
     return true;
 }
 
-template <bool BYTES>
+template <bool AUX>
 struct FinalLds {
     uint64_t key[kFinalKeyCap];
     uint32_t val[kFinalKeyCap];
-    uint32_t aux[BYTES ? kFinalKeyCap : 1];
+    uint32_t aux[AUX ? kFinalKeyCap : 1];
     uint16_t perm[kFinalKeyCap];
     uint16_t smap[kFinalCellCap];
     uint32_t words[kGroupsPerPart];
@@ -411,9 +372,11 @@ struct FinalLds {
     uint32_t gks[kGroupsPerPart];
     uint32_t gbase[kGroupsPerPart];
     uint8_t tb[kPartBuckets];
-    uint16_t big[kPartBuckets];   // buckets of two or more keys
+    uint32_t occ[kFinalCellCap / 32];   // cells taken by trial 0
+    uint32_t fl[kPartBuckets / 32];     // buckets where trial 0 collides
+    uint16_t hard[kFinalKeyCap / 2];   // buckets of two or more keys that trial 0 does not place
     uint64_t mag[16];             // remainder magic of s^2, s = 0..15
-    uint32_t nbig;
+    uint32_t nhard;
     uint32_t wsum[2][kPB / 64];
     uint32_t flags[3];   // exhausted, dup, max_t
 };
@@ -421,9 +384,9 @@ struct FinalLds {
 // smallest trial for a bucket of 2..8 keys held in registers: one 64-bit
 // occupancy mask, remainders by multiplication
 __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T, uint32_t s, const uint64_t (&kx)[8],
-                                                    uint64_t M) {
+                                                    uint64_t M, uint32_t t0 = 0) {
     const uint32_t s2 = s * s;
-    for (uint32_t t = 0; t < T; ++t) {
+    for (uint32_t t = t0; t < T; ++t) {
         const Triple c = C[t];
         uint64_t m = 0;
         bool collide = false;
@@ -440,7 +403,10 @@ __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T,
     return T;
 }
 
-template <bool BYTES>
+// AUX: an aux word travels with every key (a string key's index, or the high
+// half of a 64-bit value); STR: keys are string fingerprints, so equal keys
+// are told apart by their bytes
+template <bool AUX, bool STR>
 __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                   const uint32_t* __restrict__ aux, int aux_is_pos, uint64_t n,
                                                   Triple A, uint64_t magic, const uint64_t* __restrict__ offQ,
@@ -450,7 +416,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                                                   uint32_t* __restrict__ ctrl_flags, const int64_t* __restrict__ ctx_off,
                                                   const uint8_t* __restrict__ ctx_bytes,
                                                   const uint8_t* __restrict__ given_t) {
-    __shared__ FinalLds<BYTES> L;
+    __shared__ FinalLds<AUX> L;
     extern __shared__ Triple Cdyn[];   // the T level-two triples
     Triple* const LC = Cdyn;
     const uint32_t q = blockIdx.x, tid = threadIdx.x;
@@ -471,7 +437,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             if (i < nq) {
                 xk[k] = keys[k0 + i];
                 vk[k] = vals[k0 + i];
-                if (BYTES) ak[k] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
+                if (AUX) ak[k] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
             }
         }
     }
@@ -481,6 +447,14 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         L.words[g] = gg < G ? sizes[gg] : 0u;
     }
     if (tid < 3) L.flags[tid] = 0;
+    if (fast) {
+        for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
+        for (uint32_t b = tid; b < kPartBuckets; b += kPB) L.tb[b] = 0;
+        for (uint32_t w = tid; w < kFinalCellCap / 32; w += kPB) L.occ[w] = 0;
+        if (tid < kPartBuckets / 32) L.fl[tid] = 0;
+        if (tid < 16) L.mag[tid] = tid ? fastmod_magic(tid * tid) : 0;
+        if (tid == 0) L.nhard = 0;
+    }
     __syncthreads();
     // group statistics: where each group's keys and cells start inside the partition
     {
@@ -521,19 +495,14 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
     }
     if (fast) {
         // stage the partition's keys; ranks come from a second LDS histogram
-        for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
-        for (uint32_t b = tid; b < kPartBuckets; b += kPB) L.tb[b] = 0;
-        if (tid < 16) L.mag[tid] = tid ? fastmod_magic(tid * tid) : 0;
-        if (tid == 0) L.nbig = 0;
-        __syncthreads();
-        uint32_t lbk[KPT], rk[KPT];
+        uint32_t lbk[KPT], rk[KPT], c0k[KPT];
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
                 L.key[i] = xk[k];
                 L.val[i] = vk[k];
-                if (BYTES) L.aux[i] = ak[k];
+                if (AUX) L.aux[i] = ak[k];
                 const uint32_t lb = bucket_of(A, magic, (uint32_t)n, xk[k]) & (kPartBuckets - 1);
                 lbk[k] = lb;
                 const uint32_t sh = 4 * (lb & 7u);
@@ -541,76 +510,105 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             }
         }
         __syncthreads();
-        // group by bucket; a lone key owns its bucket's single cell; the first key of a
-        // larger bucket enlists the bucket for the level-two search
+        // group by bucket.  A lone key owns its bucket's single cell.  Every key of a
+        // larger bucket tries trial 0 at once: the second key to claim a cell marks
+        // its bucket as colliding, and only those buckets are searched below.
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
                 const uint32_t lb = lbk[k], g = lb >> 3, kk = lb & 7u, w = L.words[g];
                 const uint32_t r = rk[k], s = nib(w, kk);
+                const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
                 L.perm[L.gks[g] + prefix_cnt(w, kk) + r] = (uint16_t)i;
-                if (s == 1) L.smap[L.gbase[g] + prefix_sq(w, kk)] = (uint16_t)i;
-                else if (r == 0) L.big[atomicAdd(&L.nbig, 1u)] = (uint16_t)lb;
+                c0k[k] = off;
+                if (s == 1) {
+                    L.smap[off] = (uint16_t)i;
+                } else {
+                    if (!given_t) {
+                        const uint32_t cell = off + fastmod(mshash(LC[0], xk[k]), L.mag[s], s * s);
+                        c0k[k] = cell;
+                        const uint32_t bit = 1u << (cell & 31u), bb = 1u << (lb & 31u);
+                        if ((atomicOr(&L.occ[cell >> 5], bit) & bit) && !(atomicOr(&L.fl[lb >> 5], bb) & bb))
+                            L.hard[atomicAdd(&L.nhard, 1u)] = (uint16_t)lb;
+                    }
+                }
             }
         }
         __syncthreads();
-        const uint32_t nb = L.nbig;
-        for (uint32_t j = tid; j < nb; j += kPB) {
-            const uint32_t b = L.big[j];
+        // every cell of a bucket of two or more keys first holds a marker with the
+        // bucket's first cell; the keys overwrite their own cells below, and a cell
+        // still marked when it is written out takes the bucket's lowest occupied one
+        auto mark = [&](uint32_t b, uint32_t t) {
             const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
-            const uint32_t s = nib(w, kk), s2 = s * s;
+            const uint32_t s = nib(w, kk), off = L.gbase[g] + prefix_sq(w, kk);
+            for (uint32_t p = 0; p < s * s; ++p) L.smap[off + p] = (uint16_t)(0x8000u | off);
+            L.tb[b] = (uint8_t)t;
+            if (t) atomicMax(&L.flags[2], t);
+        };
+        for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
+            if (nib(L.words[b >> 3], b & 7u) < 2) continue;
+            if (given_t) mark(b, given_t[(uint64_t)q * kPartBuckets + b]);
+            else if (!((L.fl[b >> 5] >> (b & 31u)) & 1u)) mark(b, 0);
+        }
+        // the colliding buckets, packed so that the search occupies few waves
+        const uint32_t nh = given_t ? 0u : L.nhard;
+        for (uint32_t j = tid; j < nh; j += kPB) {
+            const uint32_t b = L.hard[j];
+            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
+            const uint32_t s = nib(w, kk);
             const uint32_t kst = L.gks[g] + prefix_cnt(w, kk);
-            const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
-            const uint64_t M = L.mag[s];
             uint32_t t;
-            if (given_t) {
-                t = given_t[(uint64_t)q * kPartBuckets + b];
-            } else if (s <= 8) {
+            if (s <= 8) {
                 uint64_t kx[8];
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i) kx[i] = i < s ? L.key[L.perm[kst + i]] : 0;
-                t = min_trial_small(LC, T, s, kx, M);
+                t = min_trial_small(LC, T, s, kx, L.mag[s], 1);
             } else {
-                t = min_trial(LC, T, s, [&](uint32_t i) { return L.key[L.perm[kst + i]]; });
+                t = min_trial(LC, T, s, [&](uint32_t i) { return L.key[L.perm[kst + i]]; }, 1);
             }
             if (t < T) {
-                for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = 0xFFFFu;
-                const Triple c = LC[t];
-                for (uint32_t i = 0; i < s; ++i) {
-                    const uint16_t who = L.perm[kst + i];
-                    L.smap[off + fastmod(mshash(c, L.key[who]), M, s2)] = who;
-                }
-                uint16_t first = 0;
-                for (uint32_t p = 0; p < s2; ++p)
-                    if (L.smap[off + p] != 0xFFFFu) {
-                        first = L.smap[off + p];
-                        break;
-                    }
-                for (uint32_t p = 0; p < s2; ++p)
-                    if (L.smap[off + p] == 0xFFFFu) L.smap[off + p] = first;
-                L.tb[b] = (uint8_t)t;
-                if (t) atomicMax(&L.flags[2], t);
+                mark(b, t);
             } else {
-                for (uint32_t p = 0; p < s2; ++p) L.smap[off + p] = L.perm[kst];
+                // no trial separates the bucket: the attempt fails; two equal keys
+                // make the build fail instead
                 bool dup = false;
                 for (uint32_t a2 = 0; a2 < s; ++a2)
                     for (uint32_t b2 = a2 + 1; b2 < s; ++b2) {
                         const uint16_t ia = L.perm[kst + a2], ib = L.perm[kst + b2];
-                        if (BYTES) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
+                        if (STR) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
                         else dup |= L.key[ia] == L.key[ib];
                     }
                 atomicOr(&L.flags[0], 1u);
                 if (dup) atomicOr(&L.flags[1], 1u);
+                mark(b, 0);   // any in-range content: the table is discarded
+            }
+        }
+        __syncthreads();
+        // keys of the larger buckets go to their cells
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) {
+            const uint32_t i = tid + k * kPB;
+            if (i < nq) {
+                const uint32_t lb = lbk[k], w = L.words[lb >> 3], s = nib(w, lb & 7u);
+                if (s >= 2) {
+                    const uint32_t t = L.tb[lb];
+                    uint32_t cell = c0k[k];
+                    if (t || given_t) cell = L.gbase[lb >> 3] + prefix_sq(w, lb & 7u) +
+                                             fastmod(mshash(LC[t], xk[k]), L.mag[s], s * s);
+                    L.smap[cell] = (uint16_t)i;
+                }
             }
         }
         __syncthreads();
         for (uint32_t p = tid; p < Sq; p += kPB) {
-            const uint16_t i = L.smap[p];
+            uint32_t i = L.smap[p];
+            if (i & 0x8000u)   // an empty cell: the bucket's lowest occupied cell (every bucket holds a key)
+                for (uint32_t p2 = i & 0x7FFFu; (i = L.smap[p2]) & 0x8000u; ++p2) {}
             Cell c;
             c.key = L.key[i];
             c.val = L.val[i];
-            c.aux = BYTES ? L.aux[i] : 0u;
+            c.aux = AUX ? L.aux[i] : 0u;
             slots[c0 + p] = c;
         }
     } else {
@@ -659,7 +657,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                     Cell cl;
                     cl.key = mine[who];
                     cl.val = vals[k0 + pos[who]];
-                    cl.aux = BYTES ? (aux_is_pos ? (uint32_t)(k0 + pos[who]) : aux[k0 + pos[who]]) : 0u;
+                    cl.aux = AUX ? (aux_is_pos ? (uint32_t)(k0 + pos[who]) : aux[k0 + pos[who]]) : 0u;
                     slots[c0 + off + p] = cl;
                 }
             }
@@ -667,7 +665,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 bool dup = false;
                 for (uint32_t a = 0; a < s; ++a)
                     for (uint32_t b2 = a + 1; b2 < s; ++b2) {
-                        if (BYTES) {
+                        if (STR) {
                             const uint32_t xa = aux_is_pos ? (uint32_t)(k0 + pos[a]) : aux[k0 + pos[a]];
                             const uint32_t xb = aux_is_pos ? (uint32_t)(k0 + pos[b2]) : aux[k0 + pos[b2]];
                             dup |= same_string(ctx_off, ctx_bytes, xa, xb);
@@ -732,36 +730,25 @@ PartPlan part_plan(uint64_t n) {
     return P;
 }
 
-uint64_t part_scan_tiles(const PartPlan& P) { return (P.matrix + kXTile - 1) / kXTile; }
+uint64_t exscan_tiles(uint64_t N) { return (N + kXTile - 1) / kXTile; }
+uint64_t part_scan_tiles(const PartPlan& P) { return exscan_tiles(P.matrix); }
 
-static void scan_matrix(const PartArgs& a, uint64_t N, hipStream_t st) {
-    const uint32_t nt = (uint32_t)((N + kXTile - 1) / kXTile);
-    hipLaunchKernelGGL(k_xscan_reduce, nt, kPB, 0, st, a.cnt, N, a.tsum);
-    hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.tsum, nt, a.tpre, nullptr, nullptr);
-    hipLaunchKernelGGL(k_xscan_down, nt, kPB, 0, st, a.cnt, N, a.tpre, a.off);
+void exscan_u32(const uint32_t* in, uint64_t N, uint32_t* tsum, uint64_t* tpre, uint32_t* out, hipStream_t st) {
+    const uint32_t nt = (uint32_t)exscan_tiles(N);
+    hipLaunchKernelGGL(k_xscan_reduce, nt, kPB, 0, st, in, N, tsum);
+    hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, tsum, nt, tpre, nullptr, nullptr);
+    hipLaunchKernelGGL(k_xscan_down, nt, kPB, 0, st, in, N, tpre, out);
 }
 
-static int scatter_variant() {
-    static int v = -1;
-    if (v < 0) {
-        const char* e = std::getenv("FKS_SCATTER_VARIANT");
-        v = (e && e[0] == 'p') ? 1 : 0;
-    }
-    return v;
-}
+static void scan_matrix(const PartArgs& a, uint64_t N, hipStream_t st) { exscan_u32(a.cnt, N, a.tsum, a.tpre, a.off, st); }
 
 template <bool AUX>
 static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin, const uint32_t* ain,
                     const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift, uint32_t mask, uint64_t* kout,
                     uint32_t* vout, uint32_t* aout, hipStream_t st) {
-    if (scatter_variant() == 1)
-        FKS_TIMED("fks_part_scatter", st,
-                  hipLaunchKernelGGL((k_dscatter_p<AUX, 16>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic,
-                                     ranges, W, shift, mask, a.off, kout, vout, aout));
-    else
-        FKS_TIMED("fks_part_scatter", st,
-                  hipLaunchKernelGGL((k_dscatter<AUX, 16>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic,
-                                     ranges, W, shift, mask, a.off, kout, vout, aout));
+    FKS_TIMED("fks_part_scatter", st,
+              hipLaunchKernelGGL((k_dscatter<AUX, 16>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
+                                 shift, mask, a.off, kout, vout, aout));
 }
 
 // Runs the partition passes of one attempt; stream-ordered outputs: offQ, the
@@ -770,12 +757,12 @@ static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin,
 int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     const PartPlan P = part_plan(a.n);
     const uint64_t n = a.n;
-    const bool bytes = a.bytes;
+    const bool aux = a.aux;
     o.plan = P;
     o.keys = a.keys;
     o.vals = a.vals;
-    o.aux = nullptr;
-    o.aux_is_pos = 1;
+    o.aux = a.aux_in;
+    o.aux_is_pos = a.aux_in ? 0 : 1;
     auto count = [&](const uint64_t* kin, const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift,
                      uint32_t mask) {
         FKS_TIMED("fks_part_count", st,
@@ -787,19 +774,21 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     } else if (P.passes == 1) {
         count(a.keys, nullptr, dim3(P.W1, 1), P.W1, 0, 255);
         scan_matrix(a, (uint64_t)kBins * P.W1, st);
-        if (bytes) scatter<true>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, 0, 255, a.k2, a.v2, a.a2, st);
-        else scatter<false>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, 0, 255, a.k2, a.v2, a.a2, st);
+        if (aux)
+            scatter<true>(a, a.keys, a.vals, a.aux_in, nullptr, dim3(P.W1, 1), P.W1, 0, 255, a.k2, a.v2, a.a2, st);
+        else
+            scatter<false>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, 0, 255, a.k2, a.v2, a.a2, st);
         hipLaunchKernelGGL(k_extract_offsets, (P.Q + 256) / 256, 256, 0, st, a.off, P.W1, 8u, P.Q, n, a.offQ);
         o.keys = a.k2;
         o.vals = a.v2;
         o.aux = a.a2;
-        o.aux_is_pos = bytes ? 0 : 1;
+        o.aux_is_pos = aux ? 0 : 1;
     } else {
         count(a.keys, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255);
         scan_matrix(a, (uint64_t)kBins * P.W1, st);
-        if (bytes)
-            scatter<true>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1, a.a1,
-                          st);
+        if (aux)
+            scatter<true>(a, a.keys, a.vals, a.aux_in, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1,
+                          a.a1, st);
         else
             scatter<false>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1,
                            a.a1, st);
@@ -807,7 +796,7 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         const uint32_t maskB = (1u << P.bitsB) - 1;
         count(a.k1, a.offA, dim3(P.W2, P.binsA), P.W2, 0, maskB);
         scan_matrix(a, (uint64_t)P.binsA * kBins * P.W2, st);
-        if (bytes)
+        if (aux)
             scatter<true>(a, a.k1, a.v1, a.a1, a.offA, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2, a.v2, a.a2, st);
         else
             scatter<false>(a, a.k1, a.v1, nullptr, a.offA, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2, a.v2, a.a2, st);
@@ -815,7 +804,7 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         o.keys = a.k2;
         o.vals = a.v2;
         o.aux = a.a2;
-        o.aux_is_pos = bytes ? 0 : 1;
+        o.aux_is_pos = aux ? 0 : 1;
     }
     FKS_TIMED("fks_part_sizes", st,
               hipLaunchKernelGGL(k_psizes, P.Q, kPB, 0, st, o.keys, n, a.A, a.magic, a.offQ, a.sizes, a.G, a.sqQ,
@@ -828,16 +817,21 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
                 hipStream_t st) {
-    if (a.bytes)
+    if (a.aux && a.str)
         FKS_TIMED("fks_part_final", st,
-                  hipLaunchKernelGGL(k_pfinal<true>, o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals, o.aux, o.aux_is_pos, a.n,
-                                     a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header, slots, flags,
-                                     ctx_off, ctx_bytes, given_t));
+                  hipLaunchKernelGGL((k_pfinal<true, true>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                                     o.aux, o.aux_is_pos, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T,
+                                     header, slots, flags, ctx_off, ctx_bytes, given_t));
+    else if (a.aux)
+        FKS_TIMED("fks_part_final", st,
+                  hipLaunchKernelGGL((k_pfinal<true, false>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                                     o.aux, o.aux_is_pos, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T,
+                                     header, slots, flags, nullptr, nullptr, given_t));
     else
         FKS_TIMED("fks_part_final", st,
-                  hipLaunchKernelGGL(k_pfinal<false>, o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals, nullptr, 1, a.n, a.A,
-                                     a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header, slots, flags, nullptr,
-                                     nullptr, given_t));
+                  hipLaunchKernelGGL((k_pfinal<false, false>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                                     nullptr, 1, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header,
+                                     slots, flags, nullptr, nullptr, given_t));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }

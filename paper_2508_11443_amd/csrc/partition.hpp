@@ -25,7 +25,9 @@ struct PartPlan {
 // Inputs, scratch and outputs of one attempt (device pointers).
 struct PartArgs {
     uint64_t n, G;
-    bool bytes;
+    bool aux;                   // an aux word travels with every key
+    bool str;                   // keys are string fingerprints
+    const uint32_t* aux_in;     // the input's aux words, or nullptr for the key index
     Triple A;
     uint64_t magic;
     const uint64_t* keys;       // the integers the construction hashes
@@ -54,6 +56,11 @@ struct PartOut {
     const uint32_t* aux;
     int aux_is_pos;
 };
+
+// Exclusive prefix sum of N u32 counts whose total is below 2^32 (three launches):
+// tsum holds exscan_tiles(N) words and tpre exscan_tiles(N) + 1 words of scratch.
+uint64_t exscan_tiles(uint64_t N);
+void exscan_u32(const uint32_t* in, uint64_t N, uint32_t* tsum, uint64_t* tpre, uint32_t* out, hipStream_t st);
 
 PartPlan part_plan(uint64_t n);
 uint64_t part_scan_tiles(const PartPlan& P);

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfks.so")
 
 FKS_OK, FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY, FKS_EBUILD, FKS_EHIP = 0, -1, -2, -3, -4, -5
+FKS_LAYOUT_SORTED, FKS_LAYOUT_EYTZINGER = 0, 1
 
 
 class FksError(RuntimeError):
@@ -52,6 +53,8 @@ SIGNATURES = [
     ("fks_params_default", None, [_VP]),
     ("fks_build_u64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_build_u64_from_array", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_u64_v64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_lookup_u64_v64", _I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
     ("fks_build_bytes", _I32, [_VP, _VP, _U64, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_lookup_u64", _I32, [_VP, _VP, _U64, _VP, _VP, _U32, _VP]),
     ("fks_contains_u64", _I32, [_VP, _VP, _U64, _VP, _VP]),
@@ -81,6 +84,11 @@ SIGNATURES = [
     ("fks_server_map", _VP, [_VP, _U32]),
     ("fks_server_destroy", None, [_VP]),
     ("fks_probe_random_reads", _I32, [_U64, _U64, _U32, _VP, ctypes.POINTER(ctypes.c_double)]),
+    ("fks_sorted_build_u64", _I32, [_VP, _VP, _U64, _U32, _VP, ctypes.POINTER(_VP)]),
+    ("fks_sorted_lookup_u64", _I32, [_VP, _VP, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_sorted_export", _I32, [_VP, _VP, _VP]),
+    ("fks_sorted_info", _I32, [_VP, _VP, _VP]),
+    ("fks_sorted_destroy", None, [_VP]),
     ("fks_prof_enable", _I32, [_I32]),
     ("fks_prof_reset", None, []),
     ("fks_prof_read", _I32, [_VP, _I32]),
@@ -211,6 +219,28 @@ def fks_build_u64_from_array(keys, vals, seed: int, c=None, T=None, R=None, stre
                                           ctypes.byref(out))
     _check(rc, "fks_build_u64_from_array")
     return FksMap(out.value, "u64")
+
+
+def fks_build_u64_v64(keys, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+    """from_array_nodup with 64-bit values (device tensor, int64 or uint64)."""
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and values differ in length")
+    p = _params(c, T, R)
+    out = ctypes.c_void_p()
+    rc = _load().fks_build_u64_v64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u64_types(), "vals"), n,
+                                   seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
+    _check(rc, "fks_build_u64_v64")
+    return FksMap(out.value, "u64v64")
+
+
+def fks_lookup_u64_v64(m: FksMap, queries, vals_out, found_out=None, missing: int = 2**64 - 1, stream=None):
+    import torch
+    rc = _load().fks_lookup_u64_v64(m.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
+                                    _dev(vals_out, _u64_types(), "vals_out"),
+                                    _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                    missing & ((1 << 64) - 1), _stream(stream))
+    _check(rc, "fks_lookup_u64_v64")
 
 
 def fks_build_bytes(offsets, data, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
@@ -492,3 +522,64 @@ def fks_probe_random_reads(buffer_bytes: int = 2 << 30, probes: int = 1 << 27, w
     _check(_load().fks_probe_random_reads(buffer_bytes, probes, width_bytes, _stream(stream), ctypes.byref(ms)),
            "fks_probe_random_reads")
     return ms.value
+
+
+# ---- comparison maps: sorted array / Eytzinger order -------------------------
+
+class FksSorted:
+    """A sorted-array or Eytzinger-layout map; released with fks_sorted_destroy."""
+
+    def __init__(self, handle: int, layout: int):
+        self._h = ctypes.c_void_p(handle)
+        self.layout = layout
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n, layout = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(_load().fks_sorted_info(self._h, ctypes.byref(n), ctypes.byref(layout)), "fks_sorted_info")
+        return {"n": n.value, "layout": layout.value}
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _load().fks_sorted_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fks_sorted_build_u64(keys, vals, layout: int = FKS_LAYOUT_SORTED, stream=None) -> FksSorted:
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and values differ in length")
+    out = ctypes.c_void_p()
+    rc = _load().fks_sorted_build_u64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
+                                      layout, _stream(stream), ctypes.byref(out))
+    _check(rc, "fks_sorted_build_u64")
+    return FksSorted(out.value, layout)
+
+
+def fks_sorted_lookup_u64(s: FksSorted, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):
+    import torch
+    rc = _load().fks_sorted_lookup_u64(s.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
+                                       _dev(vals_out, _u32_types(), "vals_out"),
+                                       _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                       missing & 0xFFFFFFFF, _stream(stream))
+    _check(rc, "fks_sorted_lookup_u64")
+
+
+def fks_sorted_export(s: FksSorted):
+    """(keys uint64[n], values uint32[n]) in layout order, as numpy arrays."""
+    import numpy as np
+    n = s.info()["n"]
+    k = np.empty(n, dtype=np.uint64)
+    v = np.empty(n, dtype=np.uint32)
+    _check(_load().fks_sorted_export(s.handle, k.ctypes.data if n else None, v.ctypes.data if n else None),
+           "fks_sorted_export")
+    return k, v

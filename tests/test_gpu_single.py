@@ -291,3 +291,51 @@ def test_rounds_schedule_retries_and_duplicates():
     with pytest.raises(fks.FksError) as e:
         gpu_build(dup, vals[:1000], 1, schedule=1)
     assert e.value.code == fks.FKS_EDUPKEY
+
+
+# ---- 64-bit values -------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 9, 1000, 5000, 300007, (1 << 20) + 77])
+def test_u64_values_bit_exact(n):
+    """Maps with 64-bit values: the scatter passes carry the high halves as aux
+    words (0, 1 and 2 passes across these sizes); table bytes and lookups equal
+    the oracle's."""
+    import torch
+    fks = _fks()
+    seed = 0x64 + n
+    announce(f"gpu single u64v64: n={n} seed={seed}")
+    keys = workloads.unique_u64(n, n + 5, dense_fraction=0.5)
+    vals = np.random.default_rng(n).integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+    m = fks.fks_build_u64_v64(to_dev(keys), to_dev(vals), seed)
+    ref = oracle.build_u64_v64(keys, vals, seed)
+    assert m.info()["kind"] == 2
+    assert_same_table(m, ref)
+    q, expect = workloads.u64_queries(keys, max(2 * n, 1000), 0.5, n + 2)
+    v = empty(q.size, "u64")
+    f = empty(q.size, "u8")
+    fks.fks_lookup_u64_v64(m, to_dev(q), v, f, missing=2**64 - 7)
+    torch.cuda.synchronize()
+    rv, rf = ref.lookup_v64(q, missing=2**64 - 7)
+    assert (to_np(f, "u8") == rf).all() and (rf == expect).all()
+    assert (to_np(v, "u64") == rv).all()
+    # membership works on this kind; 32-bit lookups are refused
+    f2 = empty(q.size, "u8")
+    fks.fks_contains_u64(m, to_dev(q), f2)
+    torch.cuda.synchronize()
+    assert (to_np(f2, "u8") == rf).all()
+    with pytest.raises(fks.FksError) as e:
+        fks.fks_lookup_u64(m, to_dev(q), empty(q.size, "u32"), f)
+    assert e.value.code == fks.FKS_EINVAL
+
+
+def test_u64_values_empty_map():
+    import torch
+    fks = _fks()
+    announce("gpu single u64v64: empty map")
+    m = fks.fks_build_u64_v64(to_dev(np.zeros(0, np.uint64)), to_dev(np.zeros(0, np.uint64)), 3)
+    q = np.array([0, 1, 2**64 - 1], np.uint64)
+    v = empty(3, "u64")
+    f = empty(3, "u8")
+    fks.fks_lookup_u64_v64(m, to_dev(q), v, f, missing=42)
+    torch.cuda.synchronize()
+    assert (to_np(v, "u64") == 42).all() and not to_np(f, "u8").any()
