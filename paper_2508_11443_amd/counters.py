@@ -14,6 +14,10 @@ A kernel-trace run (``rocprofv3 --kernel-trace --stats --output-format csv``) is
 into a markdown table of per-kernel dispatch durations and resources with
 
     python -m paper_2508_11443_amd.counters trace KERNEL_TRACE.csv
+
+and any counter run (for instance the SQ instruction counters) into a table with
+
+    python -m paper_2508_11443_amd.counters table COUNTER_COLLECTION.csv
 """
 from __future__ import annotations
 
@@ -108,9 +112,34 @@ def trace_table(trace_csv: str) -> str:
     return "\n".join(lines)
 
 
+def counter_table(csv_path: str) -> str:
+    """Per library kernel and launch size: every counter of a --pmc run, averaged over the
+    launches, with per-wave figures for the SQ instruction and cycle counters."""
+    rows = [r for r in _rows(csv_path) if "fks::" in r["Kernel_Name"]]
+    by = {}
+    for r in rows:
+        key = (_short(r["Kernel_Name"]), int(r["Grid_Size"]))
+        ent = by.setdefault(key, {})
+        ent.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for e in by.values() for c in e})
+    lines = ["| kernel | grid | " + " | ".join(names) + " | per wave: " +
+             ", ".join(n for n in names if n != "SQ_WAVES") + " |",
+             "|---|---|" + "---|" * (len(names) + 1)]
+    for (name, grid), e in sorted(by.items(), key=lambda kv: -kv[0][1]):
+        avg = {c: sum(v) / len(v) for c, v in e.items()}
+        waves = avg.get("SQ_WAVES", 0.0)
+        per = ", ".join(f"{avg[c] / waves:.0f}" for c in names if c != "SQ_WAVES" and c in avg) if waves else ""
+        lines.append(f"| {name} | {grid} | " + " | ".join(f"{avg.get(c, float('nan')):.4g}" for c in names) +
+                     f" | {per} |")
+    return "\n".join(lines)
+
+
 def main(argv):
     if len(argv) >= 3 and argv[1] == "trace":
         print(trace_table(argv[2]))
+        return
+    if len(argv) >= 3 and argv[1] == "table":
+        print(counter_table(argv[2]))
         return
     fetch_csv, write_csv, dest = argv[1:4]
     data = summarize(fetch_csv, write_csv)

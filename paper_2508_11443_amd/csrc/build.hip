@@ -126,6 +126,15 @@ static Readback* pinned_readback() {
     return buf;
 }
 
+// pinned staging for an attempt's level-two triples, so their upload is asynchronous
+static Triple* pinned_triples() {
+    static thread_local Triple* buf = nullptr;
+    if (!buf) {
+        if (hipHostMalloc((void**)&buf, sizeof(Triple) * kTMax, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    }
+    return buf;
+}
+
 static int check_params(uint64_t n, const fks_params* p, fks_params& out) {
     fks_params_default(&out);
     if (p) out = *p;
@@ -198,7 +207,11 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             release();
             return FKS_ENOMEM;
         }
-    Triple Ch[kTMax];
+    Triple* const Ch = pinned_triples();
+    if (!Ch) {
+        release();
+        return FKS_ENOMEM;
+    }
     int rc = FKS_OK;
     for (uint32_t r = 0; r < P.R; ++r) {
         const Triple A = level1_triple(M->seed, r);
@@ -215,13 +228,14 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
         PartOut o;
         if ((rc = part_prepare(a, st, o))) break;
+        // the attempt's level-two triples travel while the passes run
+        for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
+        FKS_HIP(hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st));
         FKS_HIP(hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st));
         FKS_HIP(hipStreamSynchronize(st));
         if (host->oversize) continue;
         const uint64_t S = host->S;
         if (S > (uint64_t)P.c * n) continue;
-        for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
-        FKS_HIP(hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st));
         Cell* slots = (Cell*)dev_alloc(16 * (S ? S : 1), st);
         if (!slots) {
             rc = FKS_ENOMEM;

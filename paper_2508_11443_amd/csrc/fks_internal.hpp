@@ -114,13 +114,17 @@ __host__ __device__ inline uint32_t nib(uint32_t sizes, uint32_t k) {
 }
 // sum of squared sizes of buckets 0..k-1 of a group
 __host__ __device__ inline uint32_t prefix_sq(uint32_t sizes, uint32_t k) {
+    const uint32_t v = sizes & ((k == 0) ? 0u : (0xFFFFFFFFu >> (32 - 4 * k)));
+#if defined(__HIP_DEVICE_COMPILE__)
+    // the even and the odd nibbles, one per byte, each squared and summed by a
+    // 4-way byte dot product
+    const uint32_t e = v & 0x0F0F0F0Fu, o = (v >> 4) & 0x0F0F0F0Fu;
+    return __builtin_amdgcn_udot4(e, e, __builtin_amdgcn_udot4(o, o, 0u, false), false);
+#else
     uint32_t acc = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < 7; ++i) {
-        uint32_t s = nib(sizes, i);
-        acc += (i < k) ? s * s : 0u;
-    }
+    for (uint32_t i = 0; i < 8; ++i) acc += nib(v, i) * nib(v, i);
     return acc;
+#endif
 }
 __host__ __device__ inline uint32_t prefix_cnt(uint32_t sizes, uint32_t k) {
     // keep the nibbles below bucket k, then add them up pairwise

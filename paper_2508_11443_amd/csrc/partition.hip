@@ -125,7 +125,6 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
     __shared__ uint64_t skey[(kPB * ITEMS)];
     __shared__ uint32_t sval[(kPB * ITEMS)];
     __shared__ uint32_t saux[AUX ? (kPB * ITEMS) : 1];
-    __shared__ uint8_t sbin[(kPB * ITEMS)];
     __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
     __shared__ uint32_t wsum[kPB / 64];
     static_assert(kBins == kPB, "one bin per thread");
@@ -171,14 +170,15 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
                 skey[e] = x[k];
                 sval[e] = v[k];
                 if (AUX) saux[e] = u[AUX ? k : 0];
-                sbin[e] = (uint8_t)bin[k];
             }
         }
         if (ts + (kPB * ITEMS) < b) load(ts + (kPB * ITEMS));
         __syncthreads();
         const uint32_t cnt = (uint32_t)min((uint64_t)(kPB * ITEMS), b - ts);
         for (uint32_t e = tid; e < cnt; e += kPB) {
-            const uint32_t bb = sbin[e];
+            // the bin is hashed again rather than staged: 4 KiB less LDS is a third
+            // workgroup per CU
+            const uint32_t bb = ((bucket_of(A, magic, (uint32_t)n, skey[e]) >> kPartBits) >> shift) & mask;
             const uint64_t dest = (uint64_t)run[bb] + (e - toff[bb]);
             keys_out[dest] = skey[e];
             vals_out[dest] = sval[e];
@@ -229,6 +229,28 @@ __global__ __launch_bounds__(kPB) void k_xscan_down(const uint32_t* __restrict__
         if (base + k < N) out[base + k] = run;
         run += v[k];
     }
+}
+
+// the same downsweep with 64-bit outputs; out[N] = the total (tpre[tiles])
+__global__ __launch_bounds__(kPB) void k_xscan_down64(const uint32_t* __restrict__ in, uint64_t N,
+                                                        const uint64_t* __restrict__ tpre,
+                                                        uint64_t* __restrict__ out) {
+    __shared__ uint32_t wsum[kPB / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kXTile + (uint64_t)threadIdx.x * kXItems;
+    uint32_t v[kXItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kXItems; ++k) {
+        v[k] = base + k < N ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint64_t run = tpre[blockIdx.x] + block_exscan256(s, wsum);
+#pragma unroll
+    for (uint32_t k = 0; k < kXItems; ++k) {
+        if (base + k < N) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[N] = tpre[gridDim.x];
 }
 
 // offsets of bins from a scanned count matrix: out[i] = off[((i >> bits) * 256 + (i & mask)) * W]
@@ -536,80 +558,102 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             }
         }
         __syncthreads();
-        // every cell of a bucket of two or more keys first holds a marker with the
-        // bucket's first cell; the keys overwrite their own cells below, and a cell
-        // still marked when it is written out takes the bucket's lowest occupied one
-        auto mark = [&](uint32_t b, uint32_t t) {
-            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
-            const uint32_t s = nib(w, kk), off = L.gbase[g] + prefix_sq(w, kk);
-            for (uint32_t p = 0; p < s * s; ++p) L.smap[off + p] = (uint16_t)(0x8000u | off);
-            L.tb[b] = (uint8_t)t;
-            if (t) atomicMax(&L.flags[2], t);
-        };
+        // Trials: a bucket that trial 0 places keeps t = 0 (tb is zero).  Every cell of
+        // a bucket of two or more keys is marked with the bucket's first cell; the keys
+        // overwrite their own cells below, and the write-out resolves a cell still
+        // marked to the bucket's lowest occupied cell (the fill rule).
         for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
-            if (nib(L.words[b >> 3], b & 7u) < 2) continue;
-            if (given_t) mark(b, given_t[(uint64_t)q * kPartBuckets + b]);
-            else if (!((L.fl[b >> 5] >> (b & 31u)) & 1u)) mark(b, 0);
+            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
+            const uint32_t sb = nib(w, kk);
+            if (sb < 2) continue;
+            if (given_t) {
+                const uint32_t t = given_t[(uint64_t)q * kPartBuckets + b];
+                L.tb[b] = (uint8_t)t;
+                if (t) atomicMax(&L.flags[2], t);
+            }
+            const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
+            for (uint32_t p = 0; p < sb * sb; ++p) L.smap[off + p] = (uint16_t)(0x8000u | off);
         }
-        // the colliding buckets, packed so that the search occupies few waves
+        // the colliding buckets, one lane each, trials from 1 on with the keys in registers
         const uint32_t nh = given_t ? 0u : L.nhard;
         for (uint32_t j = tid; j < nh; j += kPB) {
             const uint32_t b = L.hard[j];
-            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
-            const uint32_t s = nib(w, kk);
-            const uint32_t kst = L.gks[g] + prefix_cnt(w, kk);
+            const uint32_t w = L.words[b >> 3];
+            const uint32_t sb = nib(w, b & 7u);
+            const uint32_t kst = L.gks[b >> 3] + prefix_cnt(w, b & 7u);
             uint32_t t;
-            if (s <= 8) {
+            if (sb <= 8) {
                 uint64_t kx[8];
 #pragma unroll
-                for (uint32_t i = 0; i < 8; ++i) kx[i] = i < s ? L.key[L.perm[kst + i]] : 0;
-                t = min_trial_small(LC, T, s, kx, L.mag[s], 1);
+                for (uint32_t i = 0; i < 8; ++i) kx[i] = i < sb ? L.key[L.perm[kst + i]] : 0;
+                t = min_trial_small(LC, T, sb, kx, L.mag[sb], 1);
             } else {
-                t = min_trial(LC, T, s, [&](uint32_t i) { return L.key[L.perm[kst + i]]; }, 1);
+                t = min_trial(LC, T, sb, [&](uint32_t i) { return L.key[L.perm[kst + i]]; }, 1);
             }
             if (t < T) {
-                mark(b, t);
+                L.tb[b] = (uint8_t)t;
+                atomicMax(&L.flags[2], t);
             } else {
-                // no trial separates the bucket: the attempt fails; two equal keys
-                // make the build fail instead
+                // no trial separates the bucket: the attempt fails, or the build when
+                // two keys are equal; the cells get any in-range content
                 bool dup = false;
-                for (uint32_t a2 = 0; a2 < s; ++a2)
-                    for (uint32_t b2 = a2 + 1; b2 < s; ++b2) {
+                for (uint32_t a2 = 0; a2 < sb; ++a2)
+                    for (uint32_t b2 = a2 + 1; b2 < sb; ++b2) {
                         const uint16_t ia = L.perm[kst + a2], ib = L.perm[kst + b2];
                         if (STR) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
                         else dup |= L.key[ia] == L.key[ib];
                     }
                 atomicOr(&L.flags[0], 1u);
                 if (dup) atomicOr(&L.flags[1], 1u);
-                mark(b, 0);   // any in-range content: the table is discarded
             }
         }
         __syncthreads();
-        // keys of the larger buckets go to their cells
+        // every key of a larger bucket writes its own cell
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
-                const uint32_t lb = lbk[k], w = L.words[lb >> 3], s = nib(w, lb & 7u);
-                if (s >= 2) {
+                const uint32_t lb = lbk[k], g = lb >> 3, kk = lb & 7u, w = L.words[g];
+                const uint32_t sb = nib(w, kk);
+                if (sb >= 2) {
                     const uint32_t t = L.tb[lb];
-                    uint32_t cell = c0k[k];
-                    if (t || given_t) cell = L.gbase[lb >> 3] + prefix_sq(w, lb & 7u) +
-                                             fastmod(mshash(LC[t], xk[k]), L.mag[s], s * s);
+                    const uint32_t cell = (t || given_t) ? L.gbase[g] + prefix_sq(w, kk) +
+                                                               fastmod(mshash(LC[t], xk[k]), L.mag[sb], sb * sb)
+                                                         : c0k[k];
                     L.smap[cell] = (uint16_t)i;
                 }
             }
         }
         __syncthreads();
-        for (uint32_t p = tid; p < Sq; p += kPB) {
-            uint32_t i = L.smap[p];
-            if (i & 0x8000u)   // an empty cell: the bucket's lowest occupied cell (every bucket holds a key)
-                for (uint32_t p2 = i & 0x7FFFu; (i = L.smap[p2]) & 0x8000u; ++p2) {}
-            Cell c;
-            c.key = L.key[i];
-            c.val = L.val[i];
-            c.aux = AUX ? L.aux[i] : 0u;
-            slots[c0 + p] = c;
+        // write-out: indices first (a marked cell resolves to the bucket's lowest
+        // occupied cell; every bucket holds a key), then the records
+        constexpr uint32_t CPT = kFinalCellCap / kPB;
+        static_assert(kFinalCellCap % kPB == 0, "whole cells per thread");
+        uint32_t idx[CPT];
+#pragma unroll
+        for (uint32_t k = 0; k < CPT; ++k) {
+            const uint32_t p = tid + k * kPB;
+            idx[k] = p < Sq ? L.smap[p] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < CPT; ++k) {
+            if (idx[k] & 0x8000u) {
+                uint32_t i;
+                for (uint32_t p2 = idx[k] & 0x7FFFu; (i = L.smap[p2]) & 0x8000u; ++p2) {}
+                idx[k] = i;
+            }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < CPT; ++k) {
+            const uint32_t p = tid + k * kPB;
+            if (p < Sq) {
+                const uint32_t i = idx[k];
+                Cell c;
+                c.key = L.key[i];
+                c.val = L.val[i];
+                c.aux = AUX ? L.aux[i] : 0u;
+                slots[c0 + p] = c;
+            }
         }
     } else {
         // rare: the partition does not fit the LDS staging; every bucket gathers its
@@ -731,7 +775,7 @@ PartPlan part_plan(uint64_t n) {
 }
 
 uint64_t exscan_tiles(uint64_t N) { return (N + kXTile - 1) / kXTile; }
-uint64_t part_scan_tiles(const PartPlan& P) { return exscan_tiles(P.matrix); }
+uint64_t part_scan_tiles(const PartPlan& P) { return exscan_tiles(std::max<uint64_t>(P.matrix, P.Q)); }
 
 void exscan_u32(const uint32_t* in, uint64_t N, uint32_t* tsum, uint64_t* tpre, uint32_t* out, hipStream_t st) {
     const uint32_t nt = (uint32_t)exscan_tiles(N);
@@ -809,7 +853,13 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     FKS_TIMED("fks_part_sizes", st,
               hipLaunchKernelGGL(k_psizes, P.Q, kPB, 0, st, o.keys, n, a.A, a.magic, a.offQ, a.sizes, a.G, a.sqQ,
                                  a.oversize));
-    hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.sqQ, P.Q, a.cbase, nullptr, a.S_dev);
+    {
+        // cell bases of the partitions (exclusive scan of their sums of squares) and S
+        const uint32_t nt = (uint32_t)exscan_tiles(P.Q);
+        hipLaunchKernelGGL(k_xscan_reduce, nt, kPB, 0, st, a.sqQ, (uint64_t)P.Q, a.tsum);
+        hipLaunchKernelGGL(k_scan_counts, 1, 1024, 0, st, a.tsum, nt, a.tpre, nullptr, a.S_dev);
+        hipLaunchKernelGGL(k_xscan_down64, nt, kPB, 0, st, a.sqQ, (uint64_t)P.Q, a.tpre, a.cbase);
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
