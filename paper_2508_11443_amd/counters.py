@@ -31,19 +31,25 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GIB = 1 << 30
 
-# timing name used by the library's event timer -> (kernel symbol prefix, source file)
+# timing name used by the library's event timer -> (kernel, as its demangled name reads
+# without "void ", "fks::", argument list and spaces; source file)
 KERNELS = {
-    "fks_lookup_u64": ("fks::k_lookup_u64<true, true>", "paper_2508_11443_amd/csrc/lookup.hip"),
-    "fks_part_scatter": ("fks::k_dscatter<false>", "paper_2508_11443_amd/csrc/partition.hip"),
-    "fks_part_final": ("fks::k_pfinal<false>", "paper_2508_11443_amd/csrc/partition.hip"),
-    "fks_part_count": ("fks::k_dcount", "paper_2508_11443_amd/csrc/partition.hip"),
-    "fks_part_sizes": ("fks::k_psizes", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_lookup_u64": ("k_lookup_u64<true,true,false>", "paper_2508_11443_amd/csrc/lookup.hip"),
+    "fks_part_scatter": ("k_dscatter<false,16u>", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_final": ("k_pfinal<false,false>", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_count": ("k_dcount", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_sizes": ("k_psizes", "paper_2508_11443_amd/csrc/partition.hip"),
 }
 
 
 def src_sha(rel: str) -> str:
     with open(os.path.join(ROOT, rel), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    name = name.split("(")[0]
+    return name.replace("void ", "").replace("fks::", "").replace(" ", "")
 
 
 def _rows(path):
@@ -65,14 +71,13 @@ def summarize(fetch_csv: str, write_csv: str):
     out = {}
     for timing_name, (sym, src) in KERNELS.items():
         def per_launch(rows):
-            v = [float(r["Counter_Value"]) * 1024.0 for r in rows if r["Kernel_Name"].startswith(sym)]
-            if not v:
+            mine = [r for r in rows if _short(r["Kernel_Name"]) == sym]
+            if not mine:
                 return None
             # the benchmark's own launches are the largest grids of this kernel
-            gmax = max(int(r["Grid_Size"]) for r in rows if r["Kernel_Name"].startswith(sym))
-            v = [float(r["Counter_Value"]) * 1024.0 for r in rows
-                 if r["Kernel_Name"].startswith(sym) and int(r["Grid_Size"]) == gmax]
-            return statistics.median(v)
+            gmax = max(int(r["Grid_Size"]) for r in mine)
+            return statistics.median(float(r["Counter_Value"]) * 1024.0 for r in mine
+                                     if int(r["Grid_Size"]) == gmax)
         f, w = per_launch(fr), per_launch(wr)
         if f is None or w is None:
             continue
@@ -81,11 +86,6 @@ def summarize(fetch_csv: str, write_csv: str):
                             "hbm_bytes_per_launch": round(f * sf + w * sw),
                             "fetch_scale": round(sf, 4), "write_scale": round(sw, 4)}
     return out
-
-
-def _short(name: str) -> str:
-    name = name.split("(")[0]
-    return name.replace("void ", "").replace("fks::", "").replace(" ", "")
 
 
 def trace_table(trace_csv: str) -> str:

@@ -61,9 +61,13 @@ def absent_u64(keys_sorted: np.ndarray, count: int, rng) -> np.ndarray:
         need = count - out.size
         cand = _uniform_u64(rng, need + 16)
         if keys_sorted.size:
-            pos = np.searchsorted(keys_sorted, cand)
+            # membership through the candidates in sorted order (a cache-friendly search)
+            order = np.argsort(cand, kind="stable")
+            pos = np.searchsorted(keys_sorted, cand[order])
             pos = np.minimum(pos, keys_sorted.size - 1)
-            cand = cand[keys_sorted[pos] != cand]
+            present = np.empty(cand.size, bool)
+            present[order] = keys_sorted[pos] == cand[order]
+            cand = cand[~present]
         out = np.concatenate([out, cand])
     return out[:count]
 

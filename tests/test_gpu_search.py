@@ -80,20 +80,30 @@ def test_extremes_empty_and_duplicates(layout):
     assert err.value.code == fks.FKS_EDUPKEY
 
 
+@pytest.fixture(scope="module")
+def bench_inputs():
+    """The benchmark's 2^26 keys and needles, generated once for both layouts."""
+    n = 1 << 26
+    keys = workloads.unique_u64(n, 2026, dense_fraction=0.5)
+    order = np.argsort(keys, kind="stable")
+    q, expect = workloads.u64_queries(keys, n, 0.5, 2027)
+    hit = expect == 1
+    return keys, order, q, expect, np.searchsorted(keys, q[hit], sorter=order)
+
+
 @pytest.mark.parametrize("layout", [0, 1])
-def test_bench_size(layout):
+def test_bench_size(layout, bench_inputs):
     """2^26 keys (half uniform, half one dense run), as the benchmark builds them:
     the sorted layout must be the keys in increasing order with their values; the
     Eytzinger layout must be that array gathered in level order; 2^26 needles at
     50% hits against dictionary semantics."""
     import torch
-    n = 1 << 26
+    keys, order, q, expect, pos = bench_inputs
+    n = keys.size
     announce(f"gpu search: bench size layout={layout}")
-    keys = workloads.unique_u64(n, 2026, dense_fraction=0.5)
     vals = np.arange(n, dtype=np.uint32)
     s = _fks().fks_sorted_build_u64(to_dev(keys), to_dev(vals), layout)
     gk, gv = _fks().fks_sorted_export(s)
-    order = np.argsort(keys, kind="stable")
     if layout == 0:
         assert (gk == keys[order]).all() and (gv == order.astype(np.uint32)).all()
     else:
@@ -101,15 +111,12 @@ def test_bench_size(layout):
         # of nodes (the helper is pinned against the oracle's recursive fill)
         rng = np.random.default_rng(7)
         nodes = np.concatenate([np.arange(1, 64), rng.integers(1, n + 1, size=2000)])
-        sorted_keys = keys[order]
         for i in nodes.tolist():
-            assert gk[i - 1] == sorted_keys[searchcheck.inorder_rank(i, n)]
-            assert gv[i - 1] == order[searchcheck.inorder_rank(i, n)]
-    q, expect = workloads.u64_queries(keys, n, 0.5, 2027)
+            r = searchcheck.inorder_rank(i, n)
+            assert gk[i - 1] == keys[order[r]] and gv[i - 1] == order[r]
     v, f = gpu_lookup(s, q)
     assert (f == expect).all()
     hit = expect == 1
-    pos = np.searchsorted(keys, q[hit], sorter=order)
     assert (v[hit] == order[pos].astype(np.uint32)).all()
     assert (v[~hit] == MISSING).all()
     del s
