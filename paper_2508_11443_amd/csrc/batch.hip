@@ -64,6 +64,7 @@ struct BatchLds {
     uint32_t tsh[BT / 4];
     uint32_t wsum_a[BT / 64], wsum_b[BT / 64];
     uint32_t rng[4];
+    uint64_t mag[16];   // remainder magic of s^2, s = 0..15
     uint32_t work, oversize, exhausted, dup, max_t, S;
 };
 
@@ -114,14 +115,32 @@ __device__ inline bool bts4(uint64_t& m0, uint64_t& m1, uint64_t& m2, uint64_t& 
 }
 
 template <typename KeyAt>
-__device__ inline uint32_t first_trial(const Triple* C, uint32_t T, uint32_t s, KeyAt key_at) {
+__device__ inline uint32_t first_trial(const Triple* C, uint32_t T, uint32_t s, uint64_t M, KeyAt key_at) {
     const uint32_t s2 = s * s;
+    if (s2 <= 64) {
+        // up to 8 keys: one 64-bit occupancy mask in a register
+        for (uint32_t t = 0; t < T; ++t) {
+            const Triple c = C[t];
+            uint64_t m = 0;
+            bool collide = false;
+            for (uint32_t i = 0; i < s; ++i) {
+                const uint64_t bit = 1ull << fastmod(mshash(c, key_at(i)), M, s2);
+                if (m & bit) {
+                    collide = true;
+                    break;
+                }
+                m |= bit;
+            }
+            if (!collide) return t;
+        }
+        return T;
+    }
     for (uint32_t t = 0; t < T; ++t) {
         const Triple c = C[t];
         uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
         bool collide = false;
         for (uint32_t i = 0; i < s; ++i) {
-            if (bts4(m0, m1, m2, m3, mshash(c, key_at(i)) % s2)) {
+            if (bts4(m0, m1, m2, m3, fastmod(mshash(c, key_at(i)), M, s2))) {
                 collide = true;
                 break;
             }
@@ -140,6 +159,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
     Cell* __restrict__ grouped_s) {
     __shared__ BatchLds<BT> L;
     const uint32_t tid = threadIdx.x;
+    if (tid < 16) L.mag[tid] = tid ? fastmod_magic(tid * tid) : 0;   // published by the loop's first barrier
     for (;;) {
         if (tid == 0) L.work = atomicAdd(queue, 1u);
         __syncthreads();
@@ -257,7 +277,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                     __syncthreads();
                     const uint32_t lk = kst - K0, lz = off - Z0, s2 = s * s;
                     if (s >= 2) {
-                        t = first_trial(L.C, T, s, [&](uint32_t i) { return L.ent[lk + i].key; });
+                        t = first_trial(L.C, T, s, L.mag[s], [&](uint32_t i) { return L.ent[lk + i].key; });
                         exhausted = t == T;
                     }
                     if (s >= 1) {
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                             for (uint32_t p = 0; p < s2; ++p) L.smap[lz + p] = 0xFFFFu;
                             const Triple cc = L.C[t];
                             for (uint32_t i = 0; i < s; ++i)
-                                L.smap[lz + mshash(cc, L.ent[lk + i].key) % s2] = (uint16_t)(lk + i);
+                                L.smap[lz + fastmod(mshash(cc, L.ent[lk + i].key), L.mag[s], s2)] = (uint16_t)(lk + i);
                             uint16_t first = 0;
                             for (uint32_t p = 0; p < s2; ++p)
                                 if (L.smap[lz + p] != 0xFFFFu) {
@@ -289,7 +309,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                     for (uint32_t p = tid; p < Z1 - Z0; p += BT) slot_pool[so + Z0 + p] = L.ent[L.smap[p]];
                 } else {
                     if (s >= 2) {
-                        t = first_trial(L.C, T, s, [&](uint32_t i) { return bk[i].key; });
+                        t = first_trial(L.C, T, s, L.mag[s], [&](uint32_t i) { return bk[i].key; });
                         exhausted = t == T;
                     }
                     const uint32_t s2 = s * s;

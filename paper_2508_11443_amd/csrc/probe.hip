@@ -18,27 +18,18 @@ __device__ __forceinline__ uint64_t probe_mix(uint64_t x) {
     return x;
 }
 
-// every thread keeps kInFlight independent reads outstanding
-constexpr int kInFlight = 8;
-
 template <int VEC>
 __global__ __launch_bounds__(256) void k_probe_random(const uint4* __restrict__ buf, uint64_t mask_blocks,
                                                         uint64_t nprobe, uint32_t* __restrict__ sink) {
     uint32_t acc = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nprobe; i0 += stride * kInFlight) {
-        uint4 v[kInFlight][VEC];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nprobe;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4* p = buf + (probe_mix(i) & mask_blocks) * VEC;
 #pragma unroll
-        for (int u = 0; u < kInFlight; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * stride;
-            const uint4* p = buf + (probe_mix(i) & mask_blocks) * VEC;
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) v[u][k] = i < nprobe ? p[k] : make_uint4(0, 0, 0, 0);
+        for (int k = 0; k < VEC; ++k) {
+            const uint4 v = p[k];
+            acc ^= v.x ^ v.w;
         }
-#pragma unroll
-        for (int u = 0; u < kInFlight; ++u)
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) acc ^= v[u][k].x ^ v[u][k].w;
     }
     if (acc == 0x9E3779B9u) sink[0] = acc;   // keeps the loads alive
 }
