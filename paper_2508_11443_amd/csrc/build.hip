@@ -170,43 +170,52 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     a.str = bytes;
     a.aux_in = d_aux_in;
     a.vals = d_vals;
-    // scratch, freed when the attempts are over
+    // scratch, carved from one allocation (one allocation and one release per build), freed
+    // when the attempts are over; buffers allocated later (the rounds schedule's trials) join
+    // the owned list
     std::vector<void*> owned;
-    auto grab = [&](size_t bytes_) {
-        void* p = dev_alloc(bytes_, st);
-        owned.push_back(p);
-        return p;
-    };
     auto release = [&]() {
         for (void* p : owned) dev_free(p, st);
         owned.clear();
     };
+    size_t total = 0;
+    auto carve = [&](size_t bytes_) {   // first pass sizes, second pass hands out addresses
+        const size_t at = total;
+        total += (bytes_ + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_k1 = plan.passes >= 2 ? carve(8 * n) : 0, o_v1 = plan.passes >= 2 ? carve(4 * n) : 0;
+    const size_t o_a1 = plan.passes >= 2 && carry ? carve(4 * n) : 0;
+    const size_t o_k2 = plan.passes >= 1 ? carve(8 * n) : 0, o_v2 = plan.passes >= 1 ? carve(4 * n) : 0;
+    const size_t o_a2 = plan.passes >= 1 && carry ? carve(4 * n) : 0;
+    const size_t o_cnt = carve(4 * plan.matrix), o_off = carve(4 * plan.matrix);
+    const size_t o_tsum = carve(4 * part_scan_tiles(plan)), o_tpre = carve(8 * (part_scan_tiles(plan) + 1));
+    const size_t o_offA = carve(8 * 257), o_offQ = carve(8 * ((size_t)Q + 1)), o_sqQ = carve(4 * (size_t)Q);
+    const size_t o_cbase = carve(8 * ((size_t)Q + 1)), o_sizes = carve(4 * (size_t)Q * (kPartBuckets / 8));
+    char* base = (char*)dev_alloc(total, st);
+    if (!base) return FKS_ENOMEM;
+    owned.push_back(base);
     if (plan.passes >= 2) {
-        a.k1 = (uint64_t*)grab(8 * n);
-        a.v1 = (uint32_t*)grab(4 * n);
-        if (carry) a.a1 = (uint32_t*)grab(4 * n);
+        a.k1 = (uint64_t*)(base + o_k1);
+        a.v1 = (uint32_t*)(base + o_v1);
+        if (carry) a.a1 = (uint32_t*)(base + o_a1);
     }
     if (plan.passes >= 1) {
-        a.k2 = (uint64_t*)grab(8 * n);
-        a.v2 = (uint32_t*)grab(4 * n);
-        if (carry) a.a2 = (uint32_t*)grab(4 * n);
+        a.k2 = (uint64_t*)(base + o_k2);
+        a.v2 = (uint32_t*)(base + o_v2);
+        if (carry) a.a2 = (uint32_t*)(base + o_a2);
     }
-    a.cnt = (uint32_t*)grab(4 * plan.matrix);
-    a.off = (uint32_t*)grab(4 * plan.matrix);
-    a.tsum = (uint32_t*)grab(4 * part_scan_tiles(plan));
-    a.tpre = (uint64_t*)grab(8 * (part_scan_tiles(plan) + 1));
-    a.offA = (uint64_t*)grab(8 * 257);
-    a.offQ = (uint64_t*)grab(8 * ((size_t)Q + 1));
-    a.sqQ = (uint32_t*)grab(4 * (size_t)Q);
-    a.cbase = (uint64_t*)grab(8 * ((size_t)Q + 1));
-    a.sizes = (uint32_t*)grab(4 * (size_t)Q * (kPartBuckets / 8));
+    a.cnt = (uint32_t*)(base + o_cnt);
+    a.off = (uint32_t*)(base + o_off);
+    a.tsum = (uint32_t*)(base + o_tsum);
+    a.tpre = (uint64_t*)(base + o_tpre);
+    a.offA = (uint64_t*)(base + o_offA);
+    a.offQ = (uint64_t*)(base + o_offQ);
+    a.sqQ = (uint32_t*)(base + o_sqQ);
+    a.cbase = (uint64_t*)(base + o_cbase);
+    a.sizes = (uint32_t*)(base + o_sizes);
     a.S_dev = &ctrl->S;
     a.oversize = &ctrl->oversize;
-    for (void* p : owned)
-        if (!p) {
-            release();
-            return FKS_ENOMEM;
-        }
     Triple* const Ch = pinned_triples();
     if (!Ch) {
         release();
