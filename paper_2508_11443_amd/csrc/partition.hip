@@ -26,6 +26,9 @@ namespace fks {
 constexpr uint32_t kPB = 256;                 // threads per block, partition passes
 constexpr uint32_t kPItems = 16;              // keys per thread per tile
 constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
+// keys per thread per scatter tile: 8192-key tiles write runs of ~32 records per bin (one
+// workgroup per CU); with an aux word the records are larger and the tile stays at 4096 keys
+constexpr uint32_t kPScatterItems = 32, kPScatterItemsAux = 16;
 constexpr uint32_t kBins = 256;               // bins per scatter pass
 constexpr uint32_t kFinalKeyCap = 1280;       // keys of one partition held in LDS (mean 1024, sd 32)
 constexpr uint32_t kFinalCellCap = 3072;      // cells of one partition staged in LDS (mean <= 2048, sd ~106)
@@ -405,8 +408,21 @@ struct FinalLds {
 
 // smallest trial for a bucket of 2..8 keys held in registers: one 64-bit
 // occupancy mask, remainders by multiplication
+// largest of a small value (below 16) over the wave's active lanes
+__device__ __forceinline__ uint32_t wave_max16(uint32_t v) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 3; b >= 0; --b) {
+        const uint32_t c = m | (1u << b);
+        if (__any(v >= c)) m = c;
+    }
+    return m;
+}
+
+// smax: the largest bucket among the wave's active lanes; key slots beyond it are
+// skipped by the whole wave
 __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T, uint32_t s, const uint64_t (&kx)[8],
-                                                    uint64_t M, uint32_t t0 = 0) {
+                                                    uint64_t M, uint32_t t0 = 0, uint32_t smax = 8) {
     const uint32_t s2 = s * s;
     for (uint32_t t = t0; t < T; ++t) {
         const Triple c = C[t];
@@ -414,6 +430,7 @@ __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T,
         bool collide = false;
 #pragma unroll
         for (uint32_t i = 0; i < 8; ++i) {
+            if (i >= smax) break;
             if (i < s && !collide) {
                 const uint64_t bit = 1ull << fastmod(mshash(c, kx[i]), M, s2);
                 collide = (m & bit) != 0;
@@ -583,10 +600,11 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             const uint32_t kst = L.gks[b >> 3] + prefix_cnt(w, b & 7u);
             uint32_t t;
             if (sb <= 8) {
+                const uint32_t smax = wave_max16(sb);
                 uint64_t kx[8];
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i) kx[i] = i < sb ? L.key[L.perm[kst + i]] : 0;
-                t = min_trial_small(LC, T, sb, kx, L.mag[sb], 1);
+                t = min_trial_small(LC, T, sb, kx, L.mag[sb], 1, smax);
             } else {
                 t = min_trial(LC, T, sb, [&](uint32_t i) { return L.key[L.perm[kst + i]]; }, 1);
             }
@@ -791,7 +809,7 @@ static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin,
                     const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift, uint32_t mask, uint64_t* kout,
                     uint32_t* vout, uint32_t* aout, hipStream_t st) {
     FKS_TIMED("fks_part_scatter", st,
-              hipLaunchKernelGGL((k_dscatter<AUX, 16>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
+              hipLaunchKernelGGL((k_dscatter<AUX, AUX ? kPScatterItemsAux : kPScatterItems>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
                                  shift, mask, a.off, kout, vout, aout));
 }
 
