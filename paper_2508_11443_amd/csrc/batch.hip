@@ -30,6 +30,7 @@ namespace fks {
 
 constexpr uint32_t kBatchMaxN = 1u << 16;                  // keys per map in a batch
 constexpr uint32_t kBatchMaxG = kBatchMaxN / 8;            // groups per map
+constexpr uint32_t kBU = 4;                                // keys per thread in flight per pass
 
 // What a lookup needs about map m (64 bytes, read per needle from L2).
 struct alignas(64) LDesc {
@@ -186,13 +187,26 @@ __global__ __launch_bounds__(BT) void k_batch_build(
             __syncthreads();
             // level-one histogram; the atomic's old value is the key's rank
             bool over = false;
-            for (uint32_t i = tid; i < n; i += BT) {
-                const uint32_t j = fastmod(mshash(A, keys[ko + i]), magic, n);
-                const uint32_t sh = 4 * (j & 7u);
-                const uint32_t old = atomicAdd(&L.sizes[j >> 3], 1u << sh);
-                const uint32_t rk = (old >> sh) & 15u;
-                over |= rk == 15u;
-                rank_s[ko + i] = (uint8_t)rk;
+            // kBU keys per thread are loaded before any is hashed, so their loads overlap
+            for (uint32_t i0 = 0; i0 < n; i0 += kBU * BT) {
+                uint64_t xs[kBU];
+#pragma unroll
+                for (uint32_t u = 0; u < kBU; ++u) {
+                    const uint32_t i = i0 + u * BT + tid;
+                    xs[u] = i < n ? keys[ko + i] : 0;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kBU; ++u) {
+                    const uint32_t i = i0 + u * BT + tid;
+                    if (i < n) {
+                        const uint32_t j = fastmod(mshash(A, xs[u]), magic, n);
+                        const uint32_t sh = 4 * (j & 7u);
+                        const uint32_t old = atomicAdd(&L.sizes[j >> 3], 1u << sh);
+                        const uint32_t rk = (old >> sh) & 15u;
+                        over |= rk == 15u;
+                        rank_s[ko + i] = (uint8_t)rk;
+                    }
+                }
             }
             if (over) atomicOr(&L.oversize, 1u);
             __syncthreads();
@@ -231,16 +245,30 @@ __global__ __launch_bounds__(BT) void k_batch_build(
             }
             __syncthreads();
             // counting-sort scatter of the map's keys into its staging range
-            for (uint32_t i = tid; i < n; i += BT) {
-                const uint64_t x = keys[ko + i];
-                const uint32_t j = fastmod(mshash(A, x), magic, n);
-                const uint32_t g = j >> 3, kk = j & 7u;
-                const uint32_t pos = gscan_s[ho + g].x + prefix_cnt(L.sizes[g], kk) + rank_s[ko + i];
-                Cell e;
-                e.key = x;
-                e.val = vals[ko + i];
-                e.aux = 0;
-                grouped_s[ko + pos] = e;
+            for (uint32_t i0 = 0; i0 < n; i0 += kBU * BT) {
+                uint64_t xs[kBU];
+                uint32_t vs[kBU], rs[kBU];
+#pragma unroll
+                for (uint32_t u = 0; u < kBU; ++u) {
+                    const uint32_t i = i0 + u * BT + tid;
+                    xs[u] = i < n ? keys[ko + i] : 0;
+                    vs[u] = i < n ? vals[ko + i] : 0;
+                    rs[u] = i < n ? rank_s[ko + i] : 0;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kBU; ++u) {
+                    const uint32_t i = i0 + u * BT + tid;
+                    if (i < n) {
+                        const uint32_t j = fastmod(mshash(A, xs[u]), magic, n);
+                        const uint32_t g = j >> 3, kk = j & 7u;
+                        const uint32_t pos = gscan_s[ho + g].x + prefix_cnt(L.sizes[g], kk) + rs[u];
+                        Cell e;
+                        e.key = xs[u];
+                        e.val = vs[u];
+                        e.aux = 0;
+                        grouped_s[ko + pos] = e;
+                    }
+                }
             }
             __syncthreads();
             // level-two search and table write, BT buckets at a time
@@ -280,7 +308,30 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                         t = first_trial(L.C, T, s, L.mag[s], [&](uint32_t i) { return L.ent[lk + i].key; });
                         exhausted = t == T;
                     }
-                    if (s >= 1) {
+                    if (s == 1) {
+                        L.smap[lz] = (uint16_t)lk;   // a lone key owns its bucket's one cell
+                    } else if (s >= 2 && s <= 8 && !exhausted) {
+                        // the cells of every key from registers; each cell is written once, the
+                        // empty ones with the key of the lowest occupied cell (fill rule)
+                        const Triple cc = L.C[t];
+                        const uint64_t M = L.mag[s];
+                        uint64_t occ = 0;
+                        uint32_t lowest = s2, who = lk;
+#pragma unroll
+                        for (uint32_t i = 0; i < 8; ++i) {
+                            if (i < s) {
+                                const uint32_t h = fastmod(mshash(cc, L.ent[lk + i].key), M, s2);
+                                occ |= 1ull << h;
+                                L.smap[lz + h] = (uint16_t)(lk + i);
+                                if (h < lowest) {
+                                    lowest = h;
+                                    who = lk + i;
+                                }
+                            }
+                        }
+                        for (uint32_t p = 0; p < s2; ++p)
+                            if (!((occ >> p) & 1ull)) L.smap[lz + p] = (uint16_t)who;
+                    } else if (s >= 1) {
                         if (!exhausted) {
                             for (uint32_t p = 0; p < s2; ++p) L.smap[lz + p] = 0xFFFFu;
                             const Triple cc = L.C[t];
