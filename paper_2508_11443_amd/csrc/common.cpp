@@ -103,13 +103,14 @@ int fks_export(const fks_map* map, void* h_header, void* h_slots, uint64_t* h_co
     int prev = 0;
     FKS_HIP(hipGetDevice(&prev));
     FKS_HIP(hipSetDevice(map->device));
-    FKS_HIP(hipDeviceSynchronize());
-    uint64_t hb = 16 * ((map->n + 7) / 8);
-    if (h_header && hb) FKS_HIP(hipMemcpy(h_header, map->header, hb, hipMemcpyDeviceToHost));
-    if (h_slots && map->S) FKS_HIP(hipMemcpy(h_slots, map->slots, 16 * map->S, hipMemcpyDeviceToHost));
-    if (h_consts) FKS_HIP(hipMemcpy(h_consts, map->C, sizeof(fks::Triple) * map->T, hipMemcpyDeviceToHost));
-    FKS_HIP(hipSetDevice(prev));
-    return FKS_OK;
+    const uint64_t hb = 16 * ((map->n + 7) / 8);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && h_header && hb) e = hipMemcpy(h_header, map->header, hb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_slots && map->S) e = hipMemcpy(h_slots, map->slots, 16 * map->S, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h_consts)
+        e = hipMemcpy(h_consts, map->C, sizeof(fks::Triple) * map->T, hipMemcpyDeviceToHost);
+    (void)hipSetDevice(prev);   // the caller's device, also on failure
+    return e == hipSuccess ? FKS_OK : fks::hip_fail(e);
 }
 
 void fks_destroy(fks_map* map) {
