@@ -271,14 +271,28 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                 }
             }
             __syncthreads();
-            // level-two search and table write, BT buckets at a time
+            // level-two search and table write, BT buckets at a time.  The staged records
+            // of consecutive chunks are contiguous, so the next chunk's 2*BT records (and
+            // its group prefixes) are loaded while the current chunk is processed.
+            Cell pre0{}, pre1{};
+            auto prefetch = [&](uint32_t from) {
+                const uint32_t a = from + tid, b = from + BT + tid;
+                pre0 = a < n ? grouped_s[ko + a] : Cell{};
+                pre1 = b < n ? grouped_s[ko + b] : Cell{};
+            };
+            prefetch(0);
+            uint2 gs_next = (tid >> 3) < G ? gscan_s[ho + (tid >> 3)] : make_uint2(0, 0);
             for (uint32_t b0 = 0; b0 < n; b0 += BT) {
                 const uint32_t j = b0 + tid;
                 const uint32_t g = j >> 3, k = j & 7u;
+                const uint2 gs = gs_next;
+                {
+                    const uint32_t gn = (b0 + BT + tid) >> 3;
+                    gs_next = gn < G ? gscan_s[ho + gn] : make_uint2(0, 0);
+                }
                 uint32_t s = 0, kst, off;
                 if (g < G) {
                     const uint32_t sz = L.sizes[g];
-                    const uint2 gs = gscan_s[ho + g];
                     s = nib(sz, k);
                     kst = gs.x + prefix_cnt(sz, k);
                     off = gs.y + prefix_sq(sz, k);
@@ -301,7 +315,10 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                 bool exhausted = false;
                 const Cell* bk = grouped_s + ko + kst;
                 if (fast) {
-                    for (uint32_t p = tid; p < K1 - K0; p += BT) L.ent[p] = grouped_s[ko + K0 + p];
+                    // this chunk's records come from the window prefetched at K0
+                    if (tid < K1 - K0) L.ent[tid] = pre0;
+                    if (BT + tid < K1 - K0) L.ent[BT + tid] = pre1;
+                    prefetch(K1);
                     __syncthreads();
                     const uint32_t lk = kst - K0, lz = off - Z0, s2 = s * s;
                     if (s >= 2) {
@@ -359,6 +376,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                     __syncthreads();
                     for (uint32_t p = tid; p < Z1 - Z0; p += BT) slot_pool[so + Z0 + p] = L.ent[L.smap[p]];
                 } else {
+                    prefetch(K1);
                     if (s >= 2) {
                         t = first_trial(L.C, T, s, L.mag[s], [&](uint32_t i) { return bk[i].key; });
                         exhausted = t == T;

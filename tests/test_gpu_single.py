@@ -204,6 +204,28 @@ def test_string_map_bit_exact(n):
     assert (to_np(v, "u32") == rv).all()
 
 
+def test_string_bench_size_bit_exact():
+    """The string configuration at full size: 2^22 unique lowercase strings of 4..64 bytes
+    (as the benchmark builds them), table bytes against the oracle, 2^22 needles at 50 %
+    hits against the oracle and dictionary semantics."""
+    import torch
+    n = 1 << 22
+    announce(f"gpu single bytes: bench size n={n}")
+    off, data = workloads.random_strings(n, 303)
+    vals = np.arange(n, dtype=np.uint32)
+    m = gpu_build_bytes(off, data, vals, 7)
+    ref = oracle.build_bytes(off, data, vals, 7)
+    assert_same_table(m, ref)
+    qo, qd, qf, _ = workloads.string_queries(off, data, n, 0.5, 304)
+    v = empty(n, "u32")
+    f = empty(n, "u8")
+    _fks().fks_lookup_bytes(m, to_dev(qo), to_dev(qd), v, f, missing=MISSING)
+    torch.cuda.synchronize()
+    rv, rf = ref.lookup_bytes(qo, qd, missing=MISSING)
+    assert (to_np(f, "u8") == rf).all() and (rf == qf).all()
+    assert (to_np(v, "u32") == rv).all()
+
+
 def test_string_map_edge_cases():
     import torch
     fks = _fks()
