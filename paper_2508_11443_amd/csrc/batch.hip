@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "fks_internal.hpp"
+#include "partition.hpp"
 #include "prof.hpp"
 
 namespace fks {
@@ -462,6 +463,42 @@ __global__ __launch_bounds__(BT) void k_batch_build(
     }
 }
 
+// level-two triples of attempt 0 of every wide map
+__global__ void k_wconsts(const WideSeg* __restrict__ segs, const BDesc* __restrict__ bdesc, uint32_t nseg,
+                          uint32_t T, Triple* __restrict__ Cpool) {
+    const uint64_t total = (uint64_t)nseg * T;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t m = segs[i / T].map, t = (uint32_t)(i % T);
+        Cpool[(uint64_t)m * T + t] = level2_triple(bdesc[m].seed, 0, t);
+    }
+}
+
+// outcome of every wide map: accepted at attempt 0, or left pending (status 1) for
+// the per-workgroup kernel, which retries it from attempt 0 on
+__global__ void k_wfinish(const WideSeg* __restrict__ segs, uint32_t nseg, const uint32_t* __restrict__ flags,
+                          const uint64_t* __restrict__ cbase, uint32_t T, BDesc* __restrict__ bdesc,
+                          LDesc* __restrict__ ldesc) {
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nseg; b += gridDim.x * blockDim.x) {
+        const WideSeg& sg = segs[b];
+        if (flags[4 * b] != 0 || flags[4 * b + 1] != 0) continue;
+        BDesc d = bdesc[sg.map];
+        d.status = FKS_OK;
+        d.r = 0;
+        d.S = (uint32_t)cbase[(uint64_t)b * (kSegParts + 1) + kSegParts];
+        d.max_t = flags[4 * b + 3];
+        bdesc[sg.map] = d;
+        LDesc ld;
+        ld.n = sg.n;
+        ld.T = T;
+        ld.magic = sg.magic;
+        ld.A = sg.A;
+        ld.hdr_off = sg.hdr_off;
+        ld.slot_off = sg.slot_off;
+        ldesc[sg.map] = ld;
+    }
+}
+
 template <bool WANT_VALS, bool WANT_FOUND>
 __global__ __launch_bounds__(256) void k_batch_lookup(const LDesc* __restrict__ ldesc,
                                                         const Group* __restrict__ hdr_pool,
@@ -544,11 +581,15 @@ struct fks_batch {
 
 namespace fks {
 
-// schedule id: bits 0..1 workgroup size (0: 256, 1: 512, 2: 1024), bits 4..7 workgroups per CU
+// schedule id: bits 0..1 workgroup size (0: 256, 1: 512, 2: 1024), bits 4..7 workgroups per CU,
+// bit 8: maps of at least kWideMin keys are built by the partition passes, all of them
+// together, before the per-workgroup kernel builds the rest
+constexpr uint32_t kScheduleWide = 0x100;
+constexpr uint32_t kWideMin = 8192;
 static bool decode_schedule(uint32_t sched, int& bt, int& per_cu) {
     const uint32_t b = sched & 3u;
     per_cu = (int)((sched >> 4) & 15u);
-    if (b > 2 || per_cu < 1) return false;
+    if (b > 2 || per_cu < 1 || (sched & ~0x1F3u)) return false;
     bt = 256 << b;
     return true;
 }
@@ -567,32 +608,34 @@ uint64_t batch_class_key(uint32_t M, uint64_t total) {
 
 static uint32_t default_schedule() { return 0u | (3u << 4); }   // 256 threads, 3 per CU
 
+// the per-workgroup kernel over the first `count` maps of d_order
 static int launch_batch(fks_batch* B, const uint64_t* d_keys, const uint32_t* d_vals, const uint32_t* d_order,
-                        uint32_t* d_queue, uint8_t* rank_s, uint2* gscan_s, Cell* grouped_s, uint32_t sched,
-                        hipStream_t st) {
+                        uint32_t count, uint32_t* d_queue, uint8_t* rank_s, uint2* gscan_s, Cell* grouped_s,
+                        uint32_t sched, hipStream_t st) {
     int bt = 256, per_cu = 3;
     if (!decode_schedule(sched, bt, per_cu)) return FKS_EINVAL;
+    if (count == 0) return FKS_OK;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device);
-    const unsigned grid = (unsigned)std::max(1, std::min<int>(cus * per_cu, (int)B->M));
+    const unsigned grid = (unsigned)std::max(1, std::min<int>(cus * per_cu, (int)count));
     hipLaunchKernelGGL(k_zero_u32, 1, 64, 0, st, d_queue);
     switch (bt) {
         case 256:
             FKS_TIMED("fks_batch_build", st,
                       hipLaunchKernelGGL(k_batch_build<256>, grid, 256, 0, st, d_keys, d_vals, B->bdesc, B->ldesc,
-                                         d_order, B->M, d_queue, B->c, B->T, B->R, B->Cpool, B->hdr_pool,
+                                         d_order, count, d_queue, B->c, B->T, B->R, B->Cpool, B->hdr_pool,
                                          B->slot_pool, rank_s, gscan_s, grouped_s));
             break;
         case 512:
             FKS_TIMED("fks_batch_build", st,
                       hipLaunchKernelGGL(k_batch_build<512>, grid, 512, 0, st, d_keys, d_vals, B->bdesc, B->ldesc,
-                                         d_order, B->M, d_queue, B->c, B->T, B->R, B->Cpool, B->hdr_pool,
+                                         d_order, count, d_queue, B->c, B->T, B->R, B->Cpool, B->hdr_pool,
                                          B->slot_pool, rank_s, gscan_s, grouped_s));
             break;
         default:
             FKS_TIMED("fks_batch_build", st,
                       hipLaunchKernelGGL(k_batch_build<1024>, grid, 1024, 0, st, d_keys, d_vals, B->bdesc,
-                                         B->ldesc, d_order, B->M, d_queue, B->c, B->T, B->R, B->Cpool,
+                                         B->ldesc, d_order, count, d_queue, B->c, B->T, B->R, B->Cpool,
                                          B->hdr_pool, B->slot_pool, rank_s, gscan_s, grouped_s));
             break;
     }
@@ -705,11 +748,94 @@ extern "C" int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_val
             if (kv.first == key) sched = kv.second;
     }
     B->schedule = sched;
-    int rc = launch_batch(B, d_keys, d_vals, d_order, d_queue, rank_s, gscan_s, grouped_s, sched, st);
+    int rc = FKS_OK;
+    int dummy_bt, dummy_cu;
+    if (!decode_schedule(sched, dummy_bt, dummy_cu)) rc = FKS_EINVAL;
+    uint32_t count = M;
+    if (rc == FKS_OK && (sched & kScheduleWide)) {
+        // large maps: attempt 0 of all of them by the partition passes; the order list then
+        // holds only the small maps, and a large map that the passes reject follows below
+        std::vector<WideSeg> segs;
+        uint64_t wide_keys = 0;
+        for (uint32_t m = 0; m < M; ++m) {
+            const BDesc& d = B->host[m];
+            if (d.n < kWideMin) continue;
+            WideSeg sg;
+            sg.A = level1_triple(d.seed, 0);
+            sg.magic = fastmod_magic(d.n);
+            sg.in_lo = d.key_off;
+            sg.in_hi = d.key_off + d.n;
+            sg.hdr_off = d.hdr_off;
+            sg.slot_off = d.slot_off;
+            sg.n = d.n;
+            sg.G = (d.n + 7) / 8;
+            sg.map = m;
+            sg.c = P.c;
+            segs.push_back(sg);
+            wide_keys += d.n;
+        }
+        if (!segs.empty()) {
+            const uint32_t nseg = (uint32_t)segs.size(), W = 2;
+            WideSeg* d_segs = (WideSeg*)dev_alloc(sizeof(WideSeg) * nseg, st);
+            uint32_t* d_flags = (uint32_t*)dev_alloc(16 * (size_t)nseg, st);
+            uint64_t* d_cbase = (uint64_t*)dev_alloc(8 * (size_t)nseg * (kSegParts + 1), st);
+            void* d_scratch = dev_alloc(wide_scratch_bytes(wide_keys, nseg, W), st);
+            if (!d_segs || !d_flags || !d_cbase || !d_scratch) rc = FKS_ENOMEM;
+            if (rc == FKS_OK) {
+                e = hipMemcpyAsync(d_segs, segs.data(), sizeof(WideSeg) * nseg, hipMemcpyHostToDevice, st);
+                if (e != hipSuccess) rc = hip_fail(e);
+            }
+            if (rc == FKS_OK) {
+                hipLaunchKernelGGL(k_wconsts, (unsigned)std::min<uint64_t>(4096, ((uint64_t)nseg * P.T + 255) / 256),
+                                   256, 0, st, d_segs, B->bdesc, nseg, P.T, B->Cpool);
+                rc = wide_build(d_keys, d_vals, d_segs, nseg, wide_keys, W, B->Cpool, P.T, B->hdr_pool,
+                                B->slot_pool, d_flags, d_cbase, d_scratch, st);
+            }
+            if (rc == FKS_OK) {
+                hipLaunchKernelGGL(k_wfinish, (nseg + 255) / 256, 256, 0, st, d_segs, nseg, d_flags, d_cbase, P.T,
+                                   B->bdesc, B->ldesc);
+                e = hipGetLastError();
+                if (e != hipSuccess) rc = hip_fail(e);
+            }
+            dev_free(d_segs, st);
+            dev_free(d_flags, st);
+            dev_free(d_cbase, st);
+            dev_free(d_scratch, st);
+        }
+        if (rc == FKS_OK) {
+            std::vector<uint32_t> small;
+            for (uint32_t m : order)
+                if (B->host[m].n < kWideMin) small.push_back(m);
+            count = (uint32_t)small.size();
+            e = hipMemcpyAsync(d_order, small.data(), 4 * (size_t)count, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);   // the small list is read before it goes out of scope
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
+    }
+    if (rc == FKS_OK) rc = launch_batch(B, d_keys, d_vals, d_order, count, d_queue, rank_s, gscan_s, grouped_s, sched, st);
     if (rc == FKS_OK) {
         e = hipMemcpyAsync(B->host.data(), B->bdesc, sizeof(BDesc) * M, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (rc == FKS_OK && (sched & kScheduleWide)) {
+        // large maps the partition passes left pending go through the per-workgroup kernel
+        std::vector<uint32_t> pending;
+        for (uint32_t m = 0; m < M; ++m)
+            if (B->host[m].status == 1) pending.push_back(m);
+        if (!pending.empty()) {
+            e = hipMemcpyAsync(d_order, pending.data(), 4 * pending.size(), hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = hip_fail(e);
+            if (rc == FKS_OK)
+                rc = launch_batch(B, d_keys, d_vals, d_order, (uint32_t)pending.size(), d_queue, rank_s, gscan_s,
+                                  grouped_s, sched, st);
+            if (rc == FKS_OK) {
+                e = hipMemcpyAsync(B->host.data(), B->bdesc, sizeof(BDesc) * M, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) rc = hip_fail(e);
+            }
+        }
     }
     cleanup_scratch();
     if (rc) {
@@ -735,8 +861,10 @@ extern "C" int fks_batch_set_schedule(uint32_t M, uint64_t total_keys, uint32_t 
 }
 
 extern "C" int fks_batch_schedules(uint32_t* out, int max_entries) {
-    // every valid schedule: 256/512/1024 threads, 1..4 workgroups per CU within the LDS budget
-    static const uint32_t all[] = {0x10, 0x20, 0x30, 0x11, 0x21, 0x12};
+    // every valid schedule: 256/512/1024 threads, 1..4 workgroups per CU within the LDS budget,
+    // with and without the partition passes for the large maps
+    static const uint32_t all[] = {0x10,  0x20,  0x30,  0x11,  0x21,  0x12,
+                                   0x110, 0x120, 0x130, 0x111, 0x121, 0x112};
     const int n = (int)(sizeof(all) / sizeof(all[0]));
     if (!out) return n;
     int k = 0;

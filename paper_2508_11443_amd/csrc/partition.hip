@@ -56,9 +56,12 @@ __device__ __forceinline__ uint32_t bucket_of(const Triple& A, uint64_t magic, u
 // contiguous chunk of it and walks the chunk in tiles, so that counting and
 // scattering see the keys in the same order.
 __device__ __forceinline__ void worker_range(const uint64_t* ranges, uint64_t n, uint32_t W, uint64_t& a,
-                                             uint64_t& b) {
+                                             uint64_t& b, const WideSeg* segs = nullptr) {
     uint64_t lo = 0, hi = n;
-    if (ranges) {
+    if (segs) {
+        lo = segs[blockIdx.y].in_lo;
+        hi = segs[blockIdx.y].in_hi;
+    } else if (ranges) {
         lo = ranges[blockIdx.y];
         hi = ranges[blockIdx.y + 1];
     }
@@ -68,12 +71,19 @@ __device__ __forceinline__ void worker_range(const uint64_t* ranges, uint64_t n,
 }
 
 // counts of one worker per bin: cnt[(segment * 256 + bin) * W + worker]
+// (segs: segment blockIdx.y is a wide map of a batch, with its own keys and hash)
 __global__ __launch_bounds__(kPB) void k_dcount(const uint64_t* __restrict__ keys, uint64_t n, Triple A,
                                                   uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
-                                                  uint32_t shift, uint32_t mask, uint32_t* __restrict__ cnt) {
+                                                  uint32_t shift, uint32_t mask, uint32_t* __restrict__ cnt,
+                                                  const WideSeg* __restrict__ segs = nullptr) {
     __shared__ uint32_t bins[kBins];
     uint64_t a, b;
-    worker_range(ranges, n, W, a, b);
+    worker_range(ranges, n, W, a, b, segs);
+    if (segs) {
+        A = segs[blockIdx.y].A;
+        magic = segs[blockIdx.y].magic;
+        n = segs[blockIdx.y].n;
+    }
     for (uint32_t k = threadIdx.x; k < kBins; k += kPB) bins[k] = 0;
     __syncthreads();
     for (uint64_t ts = a; ts < b; ts += kPTile) {
@@ -124,7 +134,8 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
                                                     uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
                                                     uint32_t shift, uint32_t mask, const uint32_t* __restrict__ off,
                                                     uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-                                                    uint32_t* __restrict__ aux_out) {
+                                                    uint32_t* __restrict__ aux_out,
+                                                    const WideSeg* __restrict__ segs = nullptr) {
     __shared__ uint64_t skey[(kPB * ITEMS)];
     __shared__ uint32_t sval[(kPB * ITEMS)];
     __shared__ uint32_t saux[AUX ? (kPB * ITEMS) : 1];
@@ -132,7 +143,12 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
     __shared__ uint32_t wsum[kPB / 64];
     static_assert(kBins == kPB, "one bin per thread");
     uint64_t a, b;
-    worker_range(ranges, n, W, a, b);
+    worker_range(ranges, n, W, a, b, segs);
+    if (segs) {
+        A = segs[blockIdx.y].A;
+        magic = segs[blockIdx.y].magic;
+        n = segs[blockIdx.y].n;
+    }
     const uint32_t tid = threadIdx.x;
     run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
     // a tile's records are loaded into registers one tile ahead: the loads of
@@ -297,13 +313,27 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
 
 // per partition: 4-bit bucket sizes (written to the global size words) and the
 // partition's sum of squared sizes
+// (segs: partition q is partition q % kSegParts of wide map q / kSegParts; its
+// size words are stored at q * 128 all the same, and an oversize bucket rejects
+// only that map: oversize points to the maps' outcome words, four per map)
 __global__ __launch_bounds__(kPB) void k_psizes(const uint64_t* __restrict__ keys, uint64_t n, Triple A,
                                                   uint64_t magic, const uint64_t* __restrict__ offQ,
                                                   uint32_t* __restrict__ sizes, uint64_t G,
-                                                  uint32_t* __restrict__ sq_out, uint32_t* __restrict__ oversize) {
+                                                  uint32_t* __restrict__ sq_out, uint32_t* __restrict__ oversize,
+                                                  const WideSeg* __restrict__ segs = nullptr) {
     __shared__ uint32_t words[kGroupsPerPart];
     __shared__ uint32_t red[kPB / 64];
     const uint32_t q = blockIdx.x;
+    uint32_t qh = q;   // the partition's place among its map's partitions
+    if (segs) {
+        const WideSeg& sg = segs[q / kSegParts];
+        A = sg.A;
+        magic = sg.magic;
+        n = sg.n;
+        G = sg.G;
+        qh = q % kSegParts;
+        oversize += 4 * (q / kSegParts);
+    }
     for (uint32_t g = threadIdx.x; g < kGroupsPerPart; g += kPB) words[g] = 0;
     __syncthreads();
     const uint64_t lo = offQ[q], hi = offQ[q + 1];
@@ -331,8 +361,7 @@ __global__ __launch_bounds__(kPB) void k_psizes(const uint64_t* __restrict__ key
     uint32_t sq = 0;
     for (uint32_t g = threadIdx.x; g < kGroupsPerPart; g += kPB) {
         const uint32_t w = words[g];
-        const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
-        if (gg < G) sizes[gg] = w;
+        if ((uint64_t)qh * kGroupsPerPart + g < G) sizes[(uint64_t)q * kGroupsPerPart + g] = w;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t s = nib(w, k);
@@ -445,7 +474,12 @@ __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T,
 // AUX: an aux word travels with every key (a string key's index, or the high
 // half of a 64-bit value); STR: keys are string fingerprints, so equal keys
 // are told apart by their bytes
-template <bool AUX, bool STR>
+// MULTI: partition q is partition q % kSegParts of wide map q / kSegParts of a batch
+// (segs); the map's hash, triples (Cg + map*T), header and cells (pool offsets) come
+// from its descriptor, cbase holds kSegParts+1 map-relative cell offsets per map,
+// and ctrl_flags points to four outcome words per map (a map whose word 0 is set was
+// rejected before this kernel and is skipped)
+template <bool AUX, bool STR, bool MULTI = false>
 __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                   const uint32_t* __restrict__ aux, int aux_is_pos, uint64_t n,
                                                   Triple A, uint64_t magic, const uint64_t* __restrict__ offQ,
@@ -454,15 +488,33 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                                                   Group* __restrict__ header, Cell* __restrict__ slots,
                                                   uint32_t* __restrict__ ctrl_flags, const int64_t* __restrict__ ctx_off,
                                                   const uint8_t* __restrict__ ctx_bytes,
-                                                  const uint8_t* __restrict__ given_t) {
+                                                  const uint8_t* __restrict__ given_t,
+                                                  const WideSeg* __restrict__ segs = nullptr) {
     __shared__ FinalLds<AUX> L;
     extern __shared__ Triple Cdyn[];   // the T level-two triples
     Triple* const LC = Cdyn;
     const uint32_t q = blockIdx.x, tid = threadIdx.x;
+    uint32_t qh = q;   // the partition's place among its map's partitions
+    uint64_t cq = q;   // its entry in cbase
+    if (MULTI) {
+        const uint32_t mseg = q / kSegParts;
+        const WideSeg& sg = segs[mseg];
+        qh = q % kSegParts;
+        if (ctrl_flags[4 * mseg] != 0 || (uint64_t)qh * kPartBuckets >= sg.n) return;   // the whole block
+        A = sg.A;
+        magic = sg.magic;
+        n = sg.n;
+        G = sg.G;
+        Cg += (uint64_t)sg.map * T;
+        header += sg.hdr_off;
+        slots += sg.slot_off;
+        ctrl_flags += 4 * mseg + 1;
+        cq = (uint64_t)mseg * (kSegParts + 1) + qh;
+    }
     const uint64_t k0 = offQ[q], k1 = offQ[q + 1];
     const uint32_t nq = (uint32_t)(k1 - k0);
-    const uint64_t c0 = cbase[q];
-    const uint32_t Sq = (uint32_t)(cbase[q + 1] - c0);
+    const uint64_t c0 = cbase[cq];
+    const uint32_t Sq = (uint32_t)(cbase[cq + 1] - c0);
     const bool fast = nq <= kFinalKeyCap && Sq <= kFinalCellCap;
     // the partition's records go in flight first; the set-up below overlaps their latency
     constexpr uint32_t KPT = kFinalKeyCap / kPB;
@@ -481,10 +533,8 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         }
     }
     for (uint32_t t = tid; t < T; t += kPB) LC[t] = Cg[t];
-    for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) {
-        const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
-        L.words[g] = gg < G ? sizes[gg] : 0u;
-    }
+    for (uint32_t g = tid; g < kGroupsPerPart; g += kPB)
+        L.words[g] = (uint64_t)qh * kGroupsPerPart + g < G ? sizes[(uint64_t)q * kGroupsPerPart + g] : 0u;
     if (tid < 3) L.flags[tid] = 0;
     if (fast) {
         for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
@@ -745,7 +795,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         __syncthreads();
     }
     for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) {
-        const uint64_t gg = (uint64_t)q * kGroupsPerPart + g;
+        const uint64_t gg = (uint64_t)qh * kGroupsPerPart + g;
         if (gg < G) {
             Group h;
             h.base = (uint32_t)(c0 + L.gbase[g]);
@@ -761,6 +811,21 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         if (L.flags[0]) atomicOr(&ctrl_flags[0], 1u);
         if (L.flags[1]) atomicOr(&ctrl_flags[1], 1u);
         if (L.flags[2]) atomicMax(&ctrl_flags[2], L.flags[2]);
+    }
+}
+
+// cell offsets of every wide map's partitions (map-relative) and the map's S; a map
+// whose S exceeds c*n is rejected (outcome word 0)
+__global__ void k_wbases(const uint32_t* __restrict__ sqQ, const WideSeg* __restrict__ segs, uint32_t nseg,
+                         uint64_t* __restrict__ cbase, uint32_t* __restrict__ flags) {
+    for (uint32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < nseg; m += gridDim.x * blockDim.x) {
+        uint64_t acc = 0;
+        for (uint32_t j = 0; j < kSegParts; ++j) {
+            cbase[(uint64_t)m * (kSegParts + 1) + j] = acc;
+            acc += sqQ[(uint64_t)m * kSegParts + j];
+        }
+        cbase[(uint64_t)m * (kSegParts + 1) + kSegParts] = acc;
+        if (acc > (uint64_t)segs[m].c * segs[m].n) flags[4 * m] |= 2u;
     }
 }
 
@@ -901,6 +966,68 @@ int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T
                                      nullptr, 1, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header,
                                      slots, flags, nullptr, nullptr, given_t));
     hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
+}  // namespace fks
+
+namespace fks {
+
+// scratch of wide_build: partitioned keys and values, count matrix and its scan,
+// partition offsets, sums of squares and size words
+static size_t wide_layout(uint64_t nkeys, uint32_t nseg, uint32_t W, size_t* at) {
+    const uint64_t Q = (uint64_t)nseg * kSegParts, N = (uint64_t)nseg * kBins * W;
+    const uint64_t tiles = exscan_tiles(std::max<uint64_t>(N, Q));
+    const size_t sz[8] = {8 * nkeys, 4 * nkeys, 4 * N, 4 * N, 4 * tiles, 8 * (tiles + 1), 8 * (Q + 1),
+                          4 * Q + 4 * Q * kGroupsPerPart};
+    size_t total = 0;
+    for (int i = 0; i < 8; ++i) {
+        if (at) at[i] = total;
+        total += (sz[i] + 255) & ~(size_t)255;
+    }
+    return total;
+}
+
+size_t wide_scratch_bytes(uint64_t nkeys, uint32_t nseg, uint32_t W) { return wide_layout(nkeys, nseg, W, nullptr); }
+
+int wide_build(const uint64_t* d_keys, const uint32_t* d_vals, const WideSeg* segs, uint32_t nseg, uint64_t nkeys,
+               uint32_t W, const Triple* Cpool, uint32_t T, Group* hdr_pool, Cell* slot_pool, uint32_t* flags,
+               uint64_t* cbase, void* scratch, hipStream_t st) {
+    if (nseg == 0) return FKS_OK;
+    size_t at[8];
+    wide_layout(nkeys, nseg, W, at);
+    char* base = (char*)scratch;
+    uint64_t* k2 = (uint64_t*)(base + at[0]);
+    uint32_t* v2 = (uint32_t*)(base + at[1]);
+    uint32_t* cnt = (uint32_t*)(base + at[2]);
+    uint32_t* off = (uint32_t*)(base + at[3]);
+    uint32_t* tsum = (uint32_t*)(base + at[4]);
+    uint64_t* tpre = (uint64_t*)(base + at[5]);
+    uint64_t* offQ = (uint64_t*)(base + at[6]);
+    uint32_t* sqQ = (uint32_t*)(base + at[7]);
+    uint32_t* sizes = sqQ + (uint64_t)nseg * kSegParts;
+    const uint32_t Q = nseg * kSegParts;
+    const uint64_t N = (uint64_t)nseg * kBins * W;
+    const Triple A0{0, 0, 0};
+    hipLaunchKernelGGL(k_zero_words, (4 * nseg + 255) / 256, 256, 0, st, flags, (uint64_t)4 * nseg);
+    FKS_TIMED("fks_wide_count", st,
+              hipLaunchKernelGGL(k_dcount, dim3(W, nseg), kPB, 0, st, d_keys, nkeys, A0, 0ull, nullptr, W, 0u,
+                                 kSegParts - 1, cnt, segs));
+    exscan_u32(cnt, N, tsum, tpre, off, st);
+    FKS_TIMED("fks_wide_scatter", st,
+              hipLaunchKernelGGL((k_dscatter<false, kPScatterItems>), dim3(W, nseg), kPB, 0, st, d_keys, d_vals,
+                                 nullptr, nkeys, A0, 0ull, nullptr, W, 0u, kSegParts - 1, off, k2, v2, nullptr,
+                                 segs));
+    hipLaunchKernelGGL(k_extract_offsets, (Q + 256) / 256, 256, 0, st, off, W, 6u, Q, nkeys, offQ);
+    FKS_TIMED("fks_wide_sizes", st,
+              hipLaunchKernelGGL(k_psizes, Q, kPB, 0, st, k2, nkeys, A0, 0ull, offQ, sizes, 0ull, sqQ, flags,
+                                 segs));
+    hipLaunchKernelGGL(k_wbases, (nseg + 255) / 256, 256, 0, st, sqQ, segs, nseg, cbase, flags);
+    FKS_TIMED("fks_wide_final", st,
+              hipLaunchKernelGGL((k_pfinal<false, false, true>), Q, kPB, sizeof(Triple) * T, st, k2, v2, nullptr, 1,
+                                 nkeys, A0, 0ull, offQ, cbase, sizes, 0ull, Cpool, T, hdr_pool, slot_pool, flags,
+                                 nullptr, nullptr, nullptr, segs));
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
 

@@ -11,6 +11,21 @@ namespace fks {
 constexpr uint32_t kPartBits = 10;                   // 1024 buckets per partition
 constexpr uint32_t kPartBuckets = 1u << kPartBits;
 
+// A map of a batch built by the partition passes instead of a single workgroup
+// ("wide" map, at most 65536 keys, so at most kSegParts partitions).  Global
+// partition index = segment * kSegParts + partition within the map.
+constexpr uint32_t kSegParts = 64;
+struct WideSeg {
+    Triple A;            // level-one triple of attempt 0
+    uint64_t magic;      // remainder magic of n
+    uint64_t in_lo, in_hi;   // the map's keys in the batch input
+    uint64_t hdr_off;    // first group record of the map in the header pool
+    uint64_t slot_off;   // first cell of the map in the cell pool
+    uint32_t n, G;       // keys, groups of eight buckets
+    uint32_t map;        // index of the map in the batch
+    uint32_t c;          // space factor: the attempt fails when the map's cells exceed c*n
+};
+
 struct PartPlan {
     uint32_t Q;        // partitions
     uint32_t bits_q;   // ceil(log2 Q)
@@ -63,6 +78,19 @@ uint64_t exscan_tiles(uint64_t N);
 void exscan_u32(const uint32_t* in, uint64_t N, uint32_t* tsum, uint64_t* tpre, uint32_t* out, hipStream_t st);
 
 PartPlan part_plan(uint64_t n);
+
+// The partition passes over the wide maps of a batch (attempt 0 of each).  Inputs:
+// d_keys/d_vals (the batch input), segs (nseg device descriptors), Cpool (the maps'
+// level-two triples, T per map, at index map*T), pools.  Scratch: as allocated by the
+// caller (see wide_scratch_bytes).  Per-map outcome words flags[4*seg + 0..3]: nonzero
+// word 0 = attempt rejected (a bucket over 15 keys, or more than c*n cells), word 1 =
+// a bucket exhausted its trials, word 2 = that bucket holds equal keys, word 3 = max trial.
+// cbase[seg*(kSegParts+1) + j] receives the partition cell offsets within the map, and
+// entry kSegParts the map's cell count S.
+size_t wide_scratch_bytes(uint64_t nkeys, uint32_t nseg, uint32_t W);
+int wide_build(const uint64_t* d_keys, const uint32_t* d_vals, const WideSeg* segs, uint32_t nseg, uint64_t nkeys,
+               uint32_t W, const Triple* Cpool, uint32_t T, Group* hdr_pool, Cell* slot_pool, uint32_t* flags,
+               uint64_t* cbase, void* scratch, hipStream_t st);
 uint64_t part_scan_tiles(const PartPlan& P);
 int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o);
 // given_t: trial index of every bucket decided elsewhere (n bytes), or nullptr to search

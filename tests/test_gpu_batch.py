@@ -63,8 +63,10 @@ def test_small_batch_every_map_bit_exact():
     assert (v[exp_f == 0] == MISSING).all()
 
 
-@pytest.mark.parametrize("schedule", [0x10, 0x20, 0x30, 0x11, 0x21, 0x12])
+@pytest.mark.parametrize("schedule", [0x10, 0x20, 0x30, 0x11, 0x21, 0x12, 0x110, 0x120, 0x130, 0x111, 0x121, 0x112])
 def test_every_schedule_gives_the_same_bytes(schedule):
+    """Every schedule builds the same bytes; schedules with bit 0x100 build the maps of
+    8192 keys and more with the partition passes (sizes here reach 2^14)."""
     announce(f"gpu batch: schedule {schedule:#x}")
     fks = _fks()
     assert schedule in fks.fks_batch_schedules()
@@ -72,12 +74,40 @@ def test_every_schedule_gives_the_same_bytes(schedule):
     keys, vals, off = make_batch(sizes, 12)
     b0 = fks.fks_build_batch_u64(to_dev(keys), to_dev(vals), off.astype(np.uint64), 5, schedule=0x10)
     b1 = fks.fks_build_batch_u64(to_dev(keys), to_dev(vals), off.astype(np.uint64), 5, schedule=schedule)
-    for m in range(0, 300, 7):
+    s0, r0, S0 = b0.status()
+    s1, r1, S1 = b1.status()
+    assert (s1 == s0).all() and (r1 == r0).all() and (S1 == S0).all()
+    for m in range(300):
         a = fks.fks_batch_export(b0, m)
         c = fks.fks_batch_export(b1, m)
-        assert (a[0] == c[0]).all() and (a[1] == c[1]).all()
-    for m in (0, 1, 299):
+        assert (a[0] == c[0]).all() and (a[1] == c[1]).all() and (a[2] == c[2]).all(), m
+    big = [m for m in range(300) if off[m + 1] - off[m] >= 8192]
+    for m in sorted(set([0, 1, 299] + big[:3])):
         check_map(b1, m, keys, vals, off, 5)
+
+
+@pytest.mark.parametrize("c,T", [(4, 64), (2, 64), (4, 8)])
+def test_wide_maps_with_rejected_attempts(c, T):
+    """The partition passes take attempt 0 of every large map; a map they reject is
+    rebuilt by the per-workgroup kernel from attempt 0 on.  A space factor of 2 rejects
+    about half the attempts on space, a budget of 8 trials about half on exhaustion.
+    Every map equals the oracle's build with the same parameters."""
+    fks = _fks()
+    sizes = [65536, 8192, 8191, 20000, 100, 40000, 9000, 0, 33333, 12000, 15000, 61000]
+    announce(f"gpu batch: wide maps, c={c} T={T}")
+    keys, vals, off = make_batch(sizes, 14)
+    b = fks.fks_build_batch_u64(to_dev(keys), to_dev(vals), off.astype(np.uint64), 31, c=c, T=T, R=1024,
+                                schedule=0x130)
+    st, r, S = b.status()
+    assert (st == 0).all()
+    for m in range(len(sizes)):
+        check_map(b, m, keys, vals, off, 31, c=c, T=T, R=1024)
+    if (c, T) != (4, 64):
+        assert r.max() > 0   # some large map needed a later attempt
+    ids, q, exp_f, exp_v = workloads.batch_queries(keys, off, 50000, 0.75, 9)
+    v, f = run_lookup(b, ids, q)
+    assert (f == exp_f).all()
+    assert (v[exp_f == 1] == exp_v[exp_f == 1]).all()
 
 
 def test_batch_map_equals_single_map_build():
