@@ -248,7 +248,10 @@ int fks_batch_export(const fks_batch* batch, uint32_t index, void* h_header, voi
 void fks_batch_destroy(fks_batch* batch);
 
 /* Schedules of the batched build: bits 0-1 select 256/512/1024 threads per
-   workgroup, bits 4-7 the workgroups per CU.  fks_batch_schedules lists the
+   workgroup, bits 4-7 the workgroups per CU; bit 8 set builds the maps of at
+   least 8192 keys together through the partitioned passes first (attempt 0 of
+   each; a map they reject continues in the per-workgroup kernel), and the
+   tables are the same either way.  fks_batch_schedules lists the
    valid ones (returns their count; out may be NULL).  fks_batch_set_schedule
    records the schedule that schedule = 0 uses for batches of the same size
    class (log2 of M and of the mean map size) in this process. */

@@ -606,7 +606,8 @@ uint64_t batch_class_key(uint32_t M, uint64_t total) {
     return ((uint64_t)lm << 32) | ls;
 }
 
-static uint32_t default_schedule() { return 0u | (3u << 4); }   // 256 threads, 3 per CU
+// wide maps through the partition passes, then 512 threads, 2 per CU
+static uint32_t default_schedule() { return kScheduleWide | 1u | (2u << 4); }
 
 // the per-workgroup kernel over the first `count` maps of d_order
 static int launch_batch(fks_batch* B, const uint64_t* d_keys, const uint32_t* d_vals, const uint32_t* d_order,
