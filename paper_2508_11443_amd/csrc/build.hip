@@ -56,24 +56,6 @@ __global__ void k_zero_ctrl(Ctrl* c) {
 
 // ---- string fingerprints -----------------------------------------------------
 
-__device__ inline uint64_t fingerprint_dev(const uint8_t* __restrict__ s, uint64_t len, uint64_t beta) {
-    uint64_t acc = len % kP61;
-    uint64_t full = len / 4;
-    for (uint64_t k = 0; k < full; ++k) {
-        const uint8_t* p = s + 4 * k;
-        uint32_t w = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
-        acc = addmod61(mulmod61(acc, beta), w);
-    }
-    uint64_t rest = len - 4 * full;
-    if (rest) {
-        const uint8_t* p = s + 4 * full;
-        uint32_t w = 0;
-        for (uint64_t q = 0; q < rest; ++q) w |= (uint32_t)p[q] << (8 * q);
-        acc = addmod61(mulmod61(acc, beta), w);
-    }
-    return acc;
-}
-
 __global__ __launch_bounds__(kBlock) void k_fingerprint(const int64_t* __restrict__ off,
                                                           const uint8_t* __restrict__ bytes,
                                                           uint64_t n, uint64_t beta,
@@ -81,7 +63,8 @@ __global__ __launch_bounds__(kBlock) void k_fingerprint(const int64_t* __restric
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         int64_t a = off[i], b = off[i + 1];
-        y[i] = fingerprint_dev(bytes + a, (uint64_t)(b - a), beta);
+        uint32_t w[kChunkWords];
+        y[i] = fingerprint_words(bytes + a, (uint64_t)(b - a), beta, w);
     }
 }
 

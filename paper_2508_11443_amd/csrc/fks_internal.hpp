@@ -108,6 +108,72 @@ __host__ __device__ inline uint64_t addmod61(uint64_t a, uint64_t w) {
     return r >= kP61 ? r - kP61 : r;
 }
 
+// Bytes s[0..len), len <= 4*W, as W little-endian 32-bit words, zero past len.  They are
+// read as the aligned dwords that cover the range and shifted into place (v_alignbyte):
+// one round of independent loads instead of one load per byte.  Every dword read holds
+// at least one byte of the range, so no read touches a page the range does not touch.
+template <int W>
+__device__ __forceinline__ void load_words(const uint8_t* s, uint32_t len, uint32_t (&w)[W]) {
+    const uintptr_t at = (uintptr_t)s;
+    const uint32_t* p = (const uint32_t*)(at & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(at & 3);
+    const uint32_t nraw = len ? (sh + len + 3) >> 2 : 0;
+    uint32_t raw[W + 1];
+#pragma unroll
+    for (int k = 0; k <= W; ++k) raw[k] = (uint32_t)k < nraw ? p[k] : 0u;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const uint32_t v = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], sh);
+        const int rem = (int)len - 4 * k;   // bytes of the range in word k
+        w[k] = rem >= 4 ? v : rem <= 0 ? 0u : v & ((1u << (8 * rem)) - 1u);
+    }
+}
+
+constexpr int kChunkWords = 16;   // strings are read 64 bytes at a time
+
+// Horner step over the words of one chunk of c bytes (c <= 64)
+__device__ __forceinline__ uint64_t horner_words(uint64_t acc, const uint32_t (&w)[kChunkWords], uint32_t c,
+                                                 uint64_t beta) {
+    const uint32_t nw = (c + 3) >> 2;
+#pragma unroll
+    for (int k = 0; k < kChunkWords; ++k)
+        if ((uint32_t)k < nw) acc = addmod61(mulmod61(acc, beta), w[k]);
+    return acc;
+}
+
+// Fingerprint of s[0..len): len mod p, then one Horner step per 32-bit word (the last one
+// zero-padded).  For len <= 64, w holds the string's words on return.
+__device__ __forceinline__ uint64_t fingerprint_words(const uint8_t* s, uint64_t len, uint64_t beta,
+                                                      uint32_t (&w)[kChunkWords]) {
+    uint64_t acc = len % kP61;
+    for (uint64_t done = 0; done < len; done += 4 * kChunkWords) {
+        const uint32_t c = (uint32_t)(len - done < 4 * kChunkWords ? len - done : 4 * kChunkWords);
+        load_words<kChunkWords>(s + done, c, w);
+        acc = horner_words(acc, w, c, beta);
+    }
+    if (len == 0) {
+#pragma unroll
+        for (int k = 0; k < kChunkWords; ++k) w[k] = 0u;
+    }
+    return acc;
+}
+
+// a[0..len) == b[0..len), 64 bytes at a time
+__device__ __forceinline__ bool bytes_equal(const uint8_t* a, const uint8_t* b, uint64_t len) {
+    bool eq = true;
+    for (uint64_t done = 0; done < len && eq; done += 4 * kChunkWords) {
+        const uint32_t c = (uint32_t)(len - done < 4 * kChunkWords ? len - done : 4 * kChunkWords);
+        uint32_t u[kChunkWords], v[kChunkWords];
+        load_words<kChunkWords>(a + done, c, u);
+        load_words<kChunkWords>(b + done, c, v);
+        uint32_t diff = 0;
+#pragma unroll
+        for (int k = 0; k < kChunkWords; ++k) diff |= u[k] ^ v[k];
+        eq = diff == 0;
+    }
+    return eq;
+}
+
 // ---- header helpers ---------------------------------------------------------
 __host__ __device__ inline uint32_t nib(uint32_t sizes, uint32_t k) {
     return (sizes >> (4 * k)) & 15u;

@@ -86,25 +86,10 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
     }
 }
 
-// string needles: fingerprint, probe, then compare the stored bytes on a hit
-__device__ inline uint64_t fp_dev(const uint8_t* __restrict__ s, uint64_t len, uint64_t beta) {
-    uint64_t acc = len % kP61;
-    uint64_t full = len / 4;
-    for (uint64_t k = 0; k < full; ++k) {
-        const uint8_t* p = s + 4 * k;
-        uint32_t w = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
-        acc = addmod61(mulmod61(acc, beta), w);
-    }
-    uint64_t rest = len - 4 * full;
-    if (rest) {
-        const uint8_t* p = s + 4 * full;
-        uint32_t w = 0;
-        for (uint64_t t = 0; t < rest; ++t) w |= (uint32_t)p[t] << (8 * t);
-        acc = addmod61(mulmod61(acc, beta), w);
-    }
-    return acc;
-}
-
+// String needles: fingerprint, probe, then compare the stored bytes on a fingerprint hit.
+// The needle and the stored key are read 64 bytes at a time as aligned dwords, so each
+// costs one memory round trip; a needle of at most 64 bytes stays in registers for the
+// comparison.
 template <bool WANT_VALS>
 __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
     const Group* __restrict__ header, const Cell* __restrict__ slots, Triple A, uint64_t beta,
@@ -120,7 +105,8 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
         const int64_t a = qoff[i], b = qoff[i + 1];
         const uint64_t len = (uint64_t)(b - a);
         const uint8_t* s = qbytes + a;
-        const uint64_t y = fp_dev(s, len, beta);
+        uint32_t w[kChunkWords];
+        const uint64_t y = fingerprint_words(s, len, beta, w);
         const uint32_t j = fastmod(mshash(A, y), magic, n);
         const Group h = header[j >> 3];
         const uint32_t k = j & 7u;
@@ -133,9 +119,17 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
             if (c.key == y) {
                 const int64_t ka = koff[c.aux], kb = koff[c.aux + 1];
                 if ((uint64_t)(kb - ka) == len) {
-                    const uint8_t* t = kbytes + ka;
-                    bool eq = true;
-                    for (uint64_t q = 0; q < len && eq; ++q) eq = (t[q] == s[q]);
+                    bool eq;
+                    if (len <= 4 * kChunkWords) {
+                        uint32_t u[kChunkWords];
+                        load_words<kChunkWords>(kbytes + ka, (uint32_t)len, u);
+                        uint32_t diff = 0;
+#pragma unroll
+                        for (int q = 0; q < kChunkWords; ++q) diff |= u[q] ^ w[q];
+                        eq = diff == 0;
+                    } else {
+                        eq = bytes_equal(kbytes + ka, s, len);
+                    }
                     if (eq) {
                         hit = true;
                         v = c.val;

@@ -226,6 +226,41 @@ def test_string_bench_size_bit_exact():
     assert (to_np(v, "u32") == rv).all()
 
 
+def test_string_lengths_across_chunks():
+    """Strings of 0..300 arbitrary bytes (the kernels read them 64 bytes at a time as
+    aligned words, so lengths around multiples of 64 and every byte alignment matter):
+    table bytes against the oracle; needles are every key, and every key with its first or
+    last byte changed, one byte shorter or one byte longer."""
+    import torch
+    rng = np.random.default_rng(12)
+    lens = rng.integers(0, 301, size=3000)
+    strings = [bytes(rng.integers(0, 256, size=int(L), dtype=np.uint8)) for L in lens]
+    strings += [b"x" * L for L in (4, 63, 64, 65, 127, 128, 129, 191, 192, 193)]
+    strings = list(dict.fromkeys(strings))
+    announce(f"gpu single bytes: lengths 0..300, {len(strings)} strings")
+    off, data = workloads.to_csr(strings)
+    vals = np.arange(len(strings), dtype=np.uint32)
+    m = gpu_build_bytes(off, data, vals, 77)
+    ref = oracle.build_bytes(off, data, vals, 77)
+    assert_same_table(m, ref)
+    needles = list(strings)
+    for x in strings[:800]:
+        if x:
+            needles.append(bytes([x[0] ^ 1]) + x[1:])
+            needles.append(x[:-1] + bytes([x[-1] ^ 0x80]))
+            needles.append(x[:-1])
+        needles.append(x + b"q")
+    qo, qd = workloads.to_csr(needles)
+    v = empty(len(needles), "u32")
+    f = empty(len(needles), "u8")
+    _fks().fks_lookup_bytes(m, to_dev(qo), to_dev(qd), v, f, missing=MISSING)
+    torch.cuda.synchronize()
+    rv, rf = ref.lookup_bytes(qo, qd, missing=MISSING)
+    assert (to_np(f, "u8") == rf).all() and (to_np(v, "u32") == rv).all()
+    d = {x: i for i, x in enumerate(strings)}
+    assert to_np(f, "u8").tolist() == [1 if x in d else 0 for x in needles]
+
+
 def test_string_map_edge_cases():
     import torch
     fks = _fks()
