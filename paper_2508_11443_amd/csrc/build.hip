@@ -13,6 +13,7 @@
 // same steps on the fingerprints.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -56,25 +57,23 @@ __global__ void k_zero_ctrl(Ctrl* c) {
 
 // ---- string fingerprints -----------------------------------------------------
 
+// One lane per string.  Offsets are checked here, before any byte is read through them:
+// a pair outside [0, nbytes] or decreasing sets bad_input and reads nothing.
 __global__ __launch_bounds__(kBlock) void k_fingerprint(const int64_t* __restrict__ off,
-                                                          const uint8_t* __restrict__ bytes,
-                                                          uint64_t n, uint64_t beta,
-                                                          uint64_t* __restrict__ y) {
+                                                          const uint8_t* __restrict__ bytes, uint64_t nbytes,
+                                                          uint64_t n, uint64_t beta, uint64_t* __restrict__ y,
+                                                          Ctrl* ctrl) {
+    bool bad = false;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        int64_t a = off[i], b = off[i + 1];
+        const int64_t a = off[i], b = off[i + 1];
+        if (a < 0 || b < a || (uint64_t)b > nbytes) {
+            bad = true;
+            y[i] = 0;
+            continue;
+        }
         uint32_t w[kChunkWords];
         y[i] = fingerprint_words(bytes + a, (uint64_t)(b - a), beta, w);
-    }
-}
-
-__global__ void k_check_offsets(const int64_t* __restrict__ off, uint64_t n, uint64_t nbytes, Ctrl* ctrl) {
-    bool bad = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        int64_t a = off[i];
-        if (a < 0 || (uint64_t)a > nbytes) bad = true;
-        if (i < n && off[i + 1] < a) bad = true;
     }
     if (bad) atomicOr(&ctrl->bad_input, 1u);
 }
@@ -129,10 +128,16 @@ static int check_params(uint64_t n, const fks_params* p, fks_params& out) {
     return FKS_OK;
 }
 
-static int read_ctrl(Scratch& w, hipStream_t st) {
-    FKS_HIP(hipMemcpyAsync(w.host, w.ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st));
-    FKS_HIP(hipStreamSynchronize(st));
-    return FKS_OK;
+// Cells allocated before an attempt's final pass, which is launched without waiting for
+// the attempt's S (no host round trip between the size pass and the final pass).  S is the sum of the squared bucket sizes; with n keys hashed into n buckets
+// the sizes are close to Poisson(1), so S has mean 2n - 1 and variance about 11n (the
+// fourth moment of Poisson(1) is 15).  Eight standard deviations above the mean hold it
+// but for a negligible fraction of builds; a larger S costs one more final pass into an
+// exact allocation.  More than c*n cells are never needed: such an attempt is rejected.
+static uint64_t cells_guess(uint64_t n, uint32_t c) {
+    const uint64_t g = 2 * n + (uint64_t)(8.0 * std::sqrt(11.0 * (double)n)) + 64;
+    const uint64_t lim = (uint64_t)c * n;
+    return g < lim ? g : lim;
 }
 
 // Level-one attempts with the partitioned passes (partition.hip).
@@ -144,6 +149,9 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     const uint64_t G = (n + 7) / 8;
     const bool bytes = M->kind == 1;
     const bool carry = bytes || M->kind == 2;
+    // the per-bucket schedule runs the final pass straight after the size pass, into cells
+    // allocated from a bound on S; the paper's rounds need S on the host before their search
+    const bool direct = P.schedule == 0;
     const PartPlan plan = part_plan(n);
     const uint32_t Q = plan.Q;
     PartArgs a{};
@@ -157,6 +165,8 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     // when the attempts are over; buffers allocated later (the rounds schedule's trials) join
     // the owned list
     std::vector<void*> owned;
+    Cell* slots = nullptr;   // direct form: the cells, kept across attempts
+    uint64_t cap = 0;
     auto release = [&]() {
         for (void* p : owned) dev_free(p, st);
         owned.clear();
@@ -199,8 +209,27 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     a.sizes = (uint32_t*)(base + o_sizes);
     a.S_dev = &ctrl->S;
     a.oversize = &ctrl->oversize;
+    const uint32_t* const reject = &ctrl->oversize;   // followed by bad_input
+    if (direct) {
+        cap = cells_guess(n, P.c);
+        slots = (Cell*)dev_alloc(16 * cap, st);
+        if (!slots) {
+            release();
+            return FKS_ENOMEM;
+        }
+    }
+    auto drop_slots = [&]() {
+        dev_free(slots, st);
+        slots = nullptr;
+    };
+    auto readback = [&]() {
+        hipError_t e = hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e == hipSuccess ? FKS_OK : hip_fail(e);
+    };
     Triple* const Ch = pinned_triples();
     if (!Ch) {
+        drop_slots();
         release();
         return FKS_ENOMEM;
     }
@@ -211,25 +240,76 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         a.A = A;
         a.magic = M->magic_n;
         a.keys = d_keys_in;
+        hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
         if (bytes) {
             FKS_TIMED("fks_fingerprint", st,
                       hipLaunchKernelGGL(k_fingerprint, grid_for(n, kBlock, 65536), kBlock, 0, st, M->ctx_off,
-                                         M->ctx_bytes, n, beta, y));
+                                         M->ctx_bytes, M->ctx_nbytes, n, beta, y, ctrl));
             a.keys = y;
         }
-        hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
         PartOut o;
         if ((rc = part_prepare(a, st, o))) break;
         // the attempt's level-two triples travel while the passes run
         for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
         FKS_HIP(hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st));
+        if (direct) {
+            // the final pass follows the size pass without a host round trip; the host waits
+            // once per attempt, for the outcome
+            if ((rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off, M->ctx_bytes,
+                                  nullptr, reject, cap, st)))
+                break;
+            if ((rc = readback())) break;
+            if (host->bad_input) {
+                rc = FKS_EINVAL;
+                break;
+            }
+            if (host->oversize) continue;
+            const uint64_t S = host->S;
+            if (S > (uint64_t)P.c * n) continue;
+            if (S > cap) {
+                // more cells than the guess: the same pass again into an exact allocation
+                drop_slots();
+                cap = S;
+                slots = (Cell*)dev_alloc(16 * cap, st);
+                if (!slots) {
+                    rc = FKS_ENOMEM;
+                    break;
+                }
+                hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
+                if ((rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off,
+                                      M->ctx_bytes, nullptr, reject, cap, st)))
+                    break;
+                if ((rc = readback())) break;
+            }
+            if (host->exhausted) {
+                if (host->dup) {
+                    rc = FKS_EDUPKEY;
+                    break;
+                }
+                continue;
+            }
+            M->slots = slots;
+            slots = nullptr;
+            M->S = S;
+            M->r = r;
+            M->A = A;
+            M->beta = beta;
+            M->max_t = host->max_t;
+            M->device_bytes += 16 * cap;
+            release();
+            return FKS_OK;
+        }
         FKS_HIP(hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st));
         FKS_HIP(hipStreamSynchronize(st));
+        if (host->bad_input) {
+            rc = FKS_EINVAL;
+            break;
+        }
         if (host->oversize) continue;
         const uint64_t S = host->S;
         if (S > (uint64_t)P.c * n) continue;
-        Cell* slots = (Cell*)dev_alloc(16 * (S ? S : 1), st);
-        if (!slots) {
+        Cell* cells = (Cell*)dev_alloc(16 * (S ? S : 1), st);
+        if (!cells) {
             rc = FKS_ENOMEM;
             break;
         }
@@ -239,7 +319,7 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             // write below then only places the keys
             uint8_t* tb = (uint8_t*)dev_alloc(4 * ((n + 3) / 4), st);
             if (!tb) {
-                dev_free(slots, st);
+                dev_free(cells, st);
                 rc = FKS_ENOMEM;
                 break;
             }
@@ -249,32 +329,29 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             bool exhausted = false;
             rc = rounds_search(o.keys, n, S, A, M->magic_n, a.sizes, Ch, P.T, tb, &exhausted, st);
             if (rc) {
-                dev_free(slots, st);
+                dev_free(cells, st);
                 break;
             }
             // a bucket left after T rounds goes through the per-bucket search, which
             // reports the exhaustion (and any duplicate keys) exactly as it would alone
             if (!exhausted) given_t = tb;
         }
-        rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off, M->ctx_bytes, given_t, st);
-        if (rc == FKS_OK) {
-            hipError_t e = hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) rc = hip_fail(e);
-        }
+        rc = part_finish(a, o, M->C, P.T, M->header, cells, &ctrl->exhausted, M->ctx_off, M->ctx_bytes, given_t,
+                         nullptr, ~0ull, st);
+        if (rc == FKS_OK) rc = readback();
         if (rc) {
-            dev_free(slots, st);
+            dev_free(cells, st);
             break;
         }
         if (host->exhausted) {
-            dev_free(slots, st);
+            dev_free(cells, st);
             if (host->dup) {
                 rc = FKS_EDUPKEY;
                 break;
             }
             continue;
         }
-        M->slots = slots;
+        M->slots = cells;
         M->S = S;
         M->r = r;
         M->A = A;
@@ -284,6 +361,7 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         release();
         return FKS_OK;
     }
+    drop_slots();
     release();
     return rc ? rc : FKS_EBUILD;
 }
@@ -318,10 +396,7 @@ static int build_common(fks_map* M, const uint64_t* d_keys_in, const uint32_t* d
         if (!M->ctx_off || !M->ctx_bytes) return fail(FKS_ENOMEM);
         M->ctx_nbytes = nbytes;
         M->device_bytes += 8 * (n + 1) + nbytes;
-        hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, w.ctrl);
-        hipLaunchKernelGGL(k_check_offsets, grid_for(n + 1, kBlock, 4096), kBlock, 0, st, d_off, n, nbytes, w.ctrl);
-        if ((rc = read_ctrl(w, st))) return fail(rc);
-        if (w.host->bad_input) return fail(FKS_EINVAL);
+        // the offsets are checked by the fingerprint pass, before any byte is read through them
         FKS_HIP(hipMemcpyAsync(M->ctx_off, d_off, 8 * (n + 1), hipMemcpyDeviceToDevice, st));
         if (nbytes) FKS_HIP(hipMemcpyAsync(M->ctx_bytes, d_bytes, nbytes, hipMemcpyDeviceToDevice, st));
     }

@@ -489,7 +489,9 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                                                   uint32_t* __restrict__ ctrl_flags, const int64_t* __restrict__ ctx_off,
                                                   const uint8_t* __restrict__ ctx_bytes,
                                                   const uint8_t* __restrict__ given_t,
-                                                  const WideSeg* __restrict__ segs = nullptr) {
+                                                  const WideSeg* __restrict__ segs = nullptr,
+                                                  const uint32_t* __restrict__ reject = nullptr,
+                                                  uint64_t cap = ~0ull) {
     __shared__ FinalLds<AUX> L;
     extern __shared__ Triple Cdyn[];   // the T level-two triples
     Triple* const LC = Cdyn;
@@ -511,10 +513,15 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         ctrl_flags += 4 * mseg + 1;
         cq = (uint64_t)mseg * (kSegParts + 1) + qh;
     }
+    // an attempt already rejected by the size pass (a bucket above 15 keys) or by bad
+    // string offsets is skipped; so is a partition whose cells would end beyond the cells
+    // allocated (the attempt then runs this pass again into an exact allocation)
+    if (reject && (reject[0] | reject[1])) return;   // the whole block
     const uint64_t k0 = offQ[q], k1 = offQ[q + 1];
     const uint32_t nq = (uint32_t)(k1 - k0);
     const uint64_t c0 = cbase[cq];
     const uint32_t Sq = (uint32_t)(cbase[cq + 1] - c0);
+    if (c0 + Sq > cap) return;   // the whole block
     const bool fast = nq <= kFinalKeyCap && Sq <= kFinalCellCap;
     // the partition's records go in flight first; the set-up below overlaps their latency
     constexpr uint32_t KPT = kFinalKeyCap / kPB;
@@ -949,22 +956,22 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
 
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
-                hipStream_t st) {
+                const uint32_t* reject, uint64_t cap, hipStream_t st) {
     if (a.aux && a.str)
         FKS_TIMED("fks_part_final", st,
                   hipLaunchKernelGGL((k_pfinal<true, true>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
                                      o.aux, o.aux_is_pos, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T,
-                                     header, slots, flags, ctx_off, ctx_bytes, given_t));
+                                     header, slots, flags, ctx_off, ctx_bytes, given_t, nullptr, reject, cap));
     else if (a.aux)
         FKS_TIMED("fks_part_final", st,
                   hipLaunchKernelGGL((k_pfinal<true, false>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
                                      o.aux, o.aux_is_pos, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T,
-                                     header, slots, flags, nullptr, nullptr, given_t));
+                                     header, slots, flags, nullptr, nullptr, given_t, nullptr, reject, cap));
     else
         FKS_TIMED("fks_part_final", st,
                   hipLaunchKernelGGL((k_pfinal<false, false>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
                                      nullptr, 1, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header,
-                                     slots, flags, nullptr, nullptr, given_t));
+                                     slots, flags, nullptr, nullptr, given_t, nullptr, reject, cap));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }

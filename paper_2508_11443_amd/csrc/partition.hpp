@@ -93,9 +93,12 @@ int wide_build(const uint64_t* d_keys, const uint32_t* d_vals, const WideSeg* se
                uint64_t* cbase, void* scratch, hipStream_t st);
 uint64_t part_scan_tiles(const PartPlan& P);
 int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o);
-// given_t: trial index of every bucket decided elsewhere (n bytes), or nullptr to search
+// given_t: trial index of every bucket decided elsewhere (n bytes), or nullptr to search.
+// reject: two device words (a bucket above 15 keys, bad string offsets); when either is set
+// the pass writes nothing (nullptr: never).  cap: cells allocated at slots; a partition
+// whose cells would end beyond them writes nothing (the caller compares S with cap).
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
-                hipStream_t st);
+                const uint32_t* reject, uint64_t cap, hipStream_t st);
 
 }  // namespace fks

@@ -178,6 +178,76 @@ def test_bench_size_bit_exact():
     torch.cuda.empty_cache()
 
 
+# ---- attempts with unusual bucket sizes ------------------------------------------------
+
+def skewed_keys(n, seed, per_bucket, rng_seed, big=0):
+    """n distinct keys whose level-one buckets under attempt 0 of `seed` (the oracle's
+    constants) are mostly every per_bucket-th bucket, per_bucket keys each, so that S is
+    near per_bucket * n; with big > 0, bucket 1 receives `big` keys as well."""
+    a0, a1, b, _ = oracle.level1_consts(seed, 0)
+    rng = np.random.default_rng(rng_seed)
+    pool = np.unique(rng.integers(0, 2**64, size=(14 + 3 * big) * n, dtype=np.uint64))
+    pool = rng.permutation(pool)
+    with np.errstate(over="ignore"):
+        h = (np.uint64(a0) * (pool & np.uint64(0xFFFFFFFF)) + np.uint64(a1) * (pool >> np.uint64(32)) +
+             np.uint64(b)) >> np.uint64(32)
+    j = (h % np.uint64(n)).astype(np.int64)
+    picked = []
+    if big:
+        picked.append(pool[j == 1][:big])
+        assert picked[0].size == big
+    in_b = (j % per_bucket == 0) & (j != 1)
+    kb, jb = pool[in_b], j[in_b]
+    order = np.argsort(jb, kind="stable")
+    kb, jb = kb[order], jb[order]
+    first = np.searchsorted(jb, jb, side="left")
+    rank = np.arange(jb.size) - first
+    picked.append(kb[rank < per_bucket])
+    keys = np.concatenate(picked)[: n]
+    if keys.size < n:   # top up with keys of other buckets
+        rest = pool[~in_b & (j != 1)]
+        keys = np.concatenate([keys, rest[: n - keys.size]])
+    assert keys.size == n and np.unique(keys).size == n
+    return rng.permutation(keys)
+
+
+@pytest.mark.parametrize("n", [6000, 100003])
+def test_more_cells_than_the_first_allocation(n):
+    """Buckets of three keys in a third of the buckets: S is near 3n, above the cells the
+    build allocates before its final pass (about 2n), so the pass runs again into an
+    exact allocation.  Attempt 0 is accepted (S <= 4n); table bytes equal the oracle's."""
+    seed = 0xB16 + n
+    announce(f"gpu single u64: S above the first allocation, n={n}")
+    keys = skewed_keys(n, seed, 3, n)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.build_u64(keys, vals, seed)
+    assert ref.r == 0 and ref.S > 2.5 * n
+    m = gpu_build(keys, vals, seed)
+    assert_same_table(m, ref)
+    q, _ = workloads.u64_queries(keys, 3000, 0.5, 9)
+    v, f = gpu_lookup(m, q)
+    rv, rf = ref.lookup(q, missing=MISSING)
+    assert (f == rf).all() and (v == rv).all()
+
+
+@pytest.mark.parametrize("case", ["oversize", "space"])
+def test_rejected_first_attempt(case):
+    """Attempt 0 rejected inside the final pass: a bucket of 16 keys (oversize), or S near
+    3n with c = 2 (space).  The next attempt is accepted; bytes equal the oracle's."""
+    n = 50000
+    seed = 0x0DD + len(case)
+    announce(f"gpu single u64: first attempt rejected ({case})")
+    if case == "oversize":
+        keys, kw = skewed_keys(n, seed, 1, 77, big=16), {}
+    else:
+        keys, kw = skewed_keys(n, seed, 3, 78), {"c": 2}
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.build_u64(keys, vals, seed, **kw)
+    assert ref.r >= 1
+    m = gpu_build(keys, vals, seed, **kw)
+    assert_same_table(m, ref)
+
+
 # ---- string keys ---------------------------------------------------------------------
 
 def gpu_build_bytes(off, data, vals, seed, **kw):
