@@ -21,8 +21,10 @@
  *     only; the library never keeps them.
  *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *     Builds are ordered on the stream and synchronise the host with it
- *     (twice per level-one attempt: once to read the table size, once to
- *     read the level-two outcome).  Lookups are fully asynchronous.
+ *     once per level-one attempt, to read its outcome (twice when the table
+ *     needs more cells than the bound the build allocates first, or under
+ *     params.schedule = 1, which reads the table size before its search).
+ *     Lookups are fully asynchronous.
  *   - Return value 0 (FKS_OK) is success; negative values are the FKS_E*
  *     codes below.  Out-parameters are written only on success.
  *   - Maps are immutable after their build and may be read by any number of
