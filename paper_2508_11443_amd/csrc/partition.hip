@@ -648,9 +648,11 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
             for (uint32_t p = 0; p < sb * sb; ++p) L.smap[off + p] = (uint16_t)(0x8000u | off);
         }
-        // the colliding buckets, one lane each, trials from 1 on with the keys in registers
+        // the colliding buckets, one lane each, trials from 1 on with the keys in registers;
+        // bucket j goes to lane j / 4 of wave j % 4, so that all four SIMDs search (a packed
+        // list of ~80 buckets would otherwise occupy one and a half waves)
         const uint32_t nh = given_t ? 0u : L.nhard;
-        for (uint32_t j = tid; j < nh; j += kPB) {
+        for (uint32_t j = (tid & 63u) * (kPB / 64) + (tid >> 6); j < nh; j += kPB) {
             const uint32_t b = L.hard[j];
             const uint32_t w = L.words[b >> 3];
             const uint32_t sb = nib(w, b & 7u);
