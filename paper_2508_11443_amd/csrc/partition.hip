@@ -28,7 +28,9 @@ constexpr uint32_t kPItems = 16;              // keys per thread per tile
 constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
 // keys per thread per scatter tile: 8192-key tiles write runs of ~32 records per bin (one
 // workgroup per CU); with an aux word the records are larger and the tile stays at 4096 keys
-constexpr uint32_t kPScatterItems = 32, kPScatterItemsAux = 16;
+// scatter tiles of the single-map passes: 1024 threads x 8 records (8192 records, 101 KB of
+// LDS, one block and four waves per SIMD on a CU), or x 4 when an aux word travels
+constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 8, kPScatterItemsAux = 4;
 constexpr uint32_t kBins = 256;               // bins per scatter pass
 constexpr uint32_t kFinalKeyCap = 1280;       // keys of one partition held in LDS (mean 1024, sd 32)
 constexpr uint32_t kFinalCellCap = 3072;      // cells of one partition staged in LDS (mean <= 2048, sd ~106)
@@ -127,8 +129,9 @@ __device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t* wsum) 
 // Scatter of one worker's chunk: every tile is sorted by bin in LDS, then each
 // bin's run is written to consecutive addresses from the worker's scanned
 // offset (no device atomics; the output order is a function of the input).
-template <bool AUX, uint32_t ITEMS>
-__global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ keys,
+// BT threads per block (at least one per bin), ITEMS records per thread per tile
+template <bool AUX, uint32_t ITEMS, uint32_t BT = kPB>
+__global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ aux, uint64_t n, Triple A,
                                                     uint64_t magic, const uint64_t* __restrict__ ranges, uint32_t W,
@@ -136,12 +139,12 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
                                                     uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                     uint32_t* __restrict__ aux_out,
                                                     const WideSeg* __restrict__ segs = nullptr) {
-    __shared__ uint64_t skey[(kPB * ITEMS)];
-    __shared__ uint32_t sval[(kPB * ITEMS)];
-    __shared__ uint32_t saux[AUX ? (kPB * ITEMS) : 1];
+    __shared__ uint64_t skey[(BT * ITEMS)];
+    __shared__ uint32_t sval[(BT * ITEMS)];
+    __shared__ uint32_t saux[AUX ? (BT * ITEMS) : 1];
     __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
-    __shared__ uint32_t wsum[kPB / 64];
-    static_assert(kBins == kPB, "one bin per thread");
+    __shared__ uint32_t wsum[BT / 64];
+    static_assert(BT >= kBins && BT % 64 == 0, "one bin per thread");
     uint64_t a, b;
     worker_range(ranges, n, W, a, b, segs);
     if (segs) {
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
         n = segs[blockIdx.y].n;
     }
     const uint32_t tid = threadIdx.x;
-    run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
+    if (tid < kBins) run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
     // a tile's records are loaded into registers one tile ahead: the loads of
     // tile i+1 are in flight while tile i is written out
     uint64_t x[ITEMS];
@@ -158,20 +161,20 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
     auto load = [&](uint64_t ts) {
 #pragma unroll
         for (uint32_t k = 0; k < ITEMS; ++k) {
-            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            const uint64_t i = ts + tid + (uint64_t)k * BT;
             x[k] = i < b ? keys[i] : 0;
             v[k] = i < b ? vals[i] : 0;
             if (AUX) u[AUX ? k : 0] = i < b ? (aux ? aux[i] : (uint32_t)i) : 0;
         }
     };
     if (a < b) load(a);
-    for (uint64_t ts = a; ts < b; ts += (kPB * ITEMS)) {
-        tcnt[tid] = 0;
+    for (uint64_t ts = a; ts < b; ts += (BT * ITEMS)) {
+        if (tid < kBins) tcnt[tid] = 0;
         __syncthreads();
         uint32_t bin[ITEMS], rank[ITEMS];
 #pragma unroll
         for (uint32_t k = 0; k < ITEMS; ++k) {
-            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            const uint64_t i = ts + tid + (uint64_t)k * BT;
             if (i < b) {
                 const uint32_t q = bucket_of(A, magic, (uint32_t)n, x[k]) >> kPartBits;
                 bin[k] = (q >> shift) & mask;
@@ -179,11 +182,14 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
             }
         }
         __syncthreads();
-        toff[tid] = block_exscan256(tcnt[tid], wsum);
+        {
+            const uint32_t e = block_exscan256(tid < kBins ? tcnt[tid] : 0u, wsum);
+            if (tid < kBins) toff[tid] = e;
+        }
         __syncthreads();
 #pragma unroll
         for (uint32_t k = 0; k < ITEMS; ++k) {
-            const uint64_t i = ts + tid + (uint64_t)k * kPB;
+            const uint64_t i = ts + tid + (uint64_t)k * BT;
             if (i < b) {
                 const uint32_t e = toff[bin[k]] + rank[k];
                 skey[e] = x[k];
@@ -191,10 +197,10 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
                 if (AUX) saux[e] = u[AUX ? k : 0];
             }
         }
-        if (ts + (kPB * ITEMS) < b) load(ts + (kPB * ITEMS));
+        if (ts + (BT * ITEMS) < b) load(ts + (BT * ITEMS));
         __syncthreads();
-        const uint32_t cnt = (uint32_t)min((uint64_t)(kPB * ITEMS), b - ts);
-        for (uint32_t e = tid; e < cnt; e += kPB) {
+        const uint32_t cnt = (uint32_t)min((uint64_t)(BT * ITEMS), b - ts);
+        for (uint32_t e = tid; e < cnt; e += BT) {
             // the bin is hashed again rather than staged: 4 KiB less LDS is a third
             // workgroup per CU
             const uint32_t bb = ((bucket_of(A, magic, (uint32_t)n, skey[e]) >> kPartBits) >> shift) & mask;
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(kPB) void k_dscatter(const uint64_t* __restrict__ k
             if (AUX) aux_out[dest] = saux[e];
         }
         __syncthreads();
-        run[tid] += tcnt[tid];
+        if (tid < kBins) run[tid] += tcnt[tid];
     }
 }
 
@@ -883,7 +889,8 @@ static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin,
                     const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift, uint32_t mask, uint64_t* kout,
                     uint32_t* vout, uint32_t* aout, hipStream_t st) {
     FKS_TIMED("fks_part_scatter", st,
-              hipLaunchKernelGGL((k_dscatter<AUX, AUX ? kPScatterItemsAux : kPScatterItems>), grid, kPB, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
+              hipLaunchKernelGGL((k_dscatter<AUX, AUX ? kPScatterItemsAux : kPScatterItems, kPScatterThreads>), grid,
+                                 kPScatterThreads, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W,
                                  shift, mask, a.off, kout, vout, aout));
 }
 
@@ -1024,7 +1031,8 @@ int wide_build(const uint64_t* d_keys, const uint32_t* d_vals, const WideSeg* se
                                  kSegParts - 1, cnt, segs));
     exscan_u32(cnt, N, tsum, tpre, off, st);
     FKS_TIMED("fks_wide_scatter", st,
-              hipLaunchKernelGGL((k_dscatter<false, kPScatterItems>), dim3(W, nseg), kPB, 0, st, d_keys, d_vals,
+              hipLaunchKernelGGL((k_dscatter<false, kPScatterItems, kPScatterThreads>), dim3(W, nseg),
+                                 kPScatterThreads, 0, st, d_keys, d_vals,
                                  nullptr, nkeys, A0, 0ull, nullptr, W, 0u, kSegParts - 1, off, k2, v2, nullptr,
                                  segs));
     hipLaunchKernelGGL(k_extract_offsets, (Q + 256) / 256, 256, 0, st, off, W, 6u, Q, nkeys, offQ);
