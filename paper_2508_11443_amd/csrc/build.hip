@@ -6,9 +6,11 @@
 // partition of 1024 consecutive buckets; one or two radix passes group the
 // records by partition; a per-partition histogram gives the bucket sizes and
 // the partition's sum of squared sizes, and their exclusive scan the table size
-// S = sum s^2 (the offsets of Section 2.2).  S is read back to check S <= c*n and
-// to size the cell array; then one workgroup per partition searches level two
-// (make_2) and writes the cells and group headers.
+// S = sum s^2 (the offsets of Section 2.2); then one workgroup per partition
+// searches level two (make_2) and writes the cells and group headers into cells
+// allocated from a bound on S.  The host reads the attempt's outcome once:
+// S <= c*n, no bucket above 15 keys, every bucket separated (and S within the
+// bound, else the final pass runs again into an exact allocation).
 // String maps first fingerprint every key with the attempt's base and run the
 // same steps on the fingerprints.
 #include <hip/hip_runtime.h>
@@ -129,8 +131,9 @@ static int check_params(uint64_t n, const fks_params* p, fks_params& out) {
 }
 
 // Cells allocated before an attempt's final pass, which is launched without waiting for
-// the attempt's S (no host round trip between the size pass and the final pass).  S is the sum of the squared bucket sizes; with n keys hashed into n buckets
-// the sizes are close to Poisson(1), so S has mean 2n - 1 and variance about 11n (the
+// the attempt's S (no host round trip between the size pass and the final pass).  S is
+// the sum of the squared bucket sizes; with n keys hashed into n buckets the sizes are
+// close to Poisson(1), so S has mean 2n - 1 and variance about 11n (the
 // fourth moment of Poisson(1) is 15).  Eight standard deviations above the mean hold it
 // but for a negligible fraction of builds; a larger S costs one more final pass into an
 // exact allocation.  More than c*n cells are never needed: such an attempt is rejected.
