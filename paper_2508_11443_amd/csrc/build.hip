@@ -187,6 +187,7 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     const size_t o_cnt = carve(4 * plan.matrix), o_off = carve(4 * plan.matrix);
     const size_t o_tsum = carve(4 * part_scan_tiles(plan)), o_tpre = carve(8 * (part_scan_tiles(plan) + 1));
     const size_t o_offA = carve(8 * 257), o_offQ = carve(8 * ((size_t)Q + 1)), o_sqQ = carve(4 * (size_t)Q);
+    const size_t o_offAB = plan.passes == 3 ? carve(8 * ((size_t)plan.binsAB + 1)) : 0;
     const size_t o_cbase = carve(8 * ((size_t)Q + 1)), o_sizes = carve(4 * (size_t)Q * (kPartBuckets / 8));
     char* base = (char*)dev_alloc(total, st);
     if (!base) return FKS_ENOMEM;
@@ -206,6 +207,7 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     a.tsum = (uint32_t*)(base + o_tsum);
     a.tpre = (uint64_t*)(base + o_tpre);
     a.offA = (uint64_t*)(base + o_offA);
+    if (plan.passes == 3) a.offAB = (uint64_t*)(base + o_offAB);
     a.offQ = (uint64_t*)(base + o_offQ);
     a.sqQ = (uint32_t*)(base + o_sqQ);
     a.cbase = (uint64_t*)(base + o_cbase);

@@ -859,16 +859,26 @@ PartPlan part_plan(uint64_t n) {
     } else if (bits <= 8) {
         P.passes = 1;
         P.binsA = P.Q;
-    } else {
+    } else if (bits <= 16) {
         P.passes = 2;
         P.shiftA = bits - 8;
         P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
         P.bitsB = P.shiftA;
         P.W2 = clampu((n / P.binsA + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
+    } else {
+        P.passes = 3;
+        P.shiftA = bits - 8;
+        P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
+        P.bitsC = bits - 16;
+        P.bitsB = 8;
+        P.binsAB = (uint32_t)((P.Q + (1u << P.bitsC) - 1) >> P.bitsC);
+        P.W2 = clampu((n / P.binsA + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
+        P.W3 = clampu((n / P.binsAB + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
     }
     uint64_t m1 = (uint64_t)kBins * P.W1;
-    uint64_t m2 = P.passes == 2 ? (uint64_t)P.binsA * kBins * P.W2 : 0;
-    P.matrix = m1 > m2 ? m1 : m2;
+    uint64_t m2 = P.passes >= 2 ? (uint64_t)P.binsA * kBins * P.W2 : 0;
+    uint64_t m3 = P.passes == 3 ? (uint64_t)P.binsAB * kBins * P.W3 : 0;
+    P.matrix = std::max(m1, std::max(m2, m3));
     return P;
 }
 
@@ -926,7 +936,7 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         o.vals = a.v2;
         o.aux = a.a2;
         o.aux_is_pos = aux ? 0 : 1;
-    } else {
+    } else if (P.passes == 2) {
         count(a.keys, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255);
         scan_matrix(a, (uint64_t)kBins * P.W1, st);
         if (aux)
@@ -947,6 +957,40 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         o.keys = a.k2;
         o.vals = a.v2;
         o.aux = a.a2;
+        o.aux_is_pos = aux ? 0 : 1;
+    } else {
+        // top 8 bits into k1, the middle 8 bits within each first-level bin into k2, the
+        // low bits within each second-level bin back into k1
+        count(a.keys, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255);
+        scan_matrix(a, (uint64_t)kBins * P.W1, st);
+        if (aux)
+            scatter<true>(a, a.keys, a.vals, a.aux_in, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1,
+                          a.a1, st);
+        else
+            scatter<false>(a, a.keys, a.vals, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255, a.k1, a.v1,
+                           a.a1, st);
+        hipLaunchKernelGGL(k_extract_offsets, (P.binsA + 256) / 256, 256, 0, st, a.off, P.W1, 8u, P.binsA, n, a.offA);
+        count(a.k1, a.offA, dim3(P.W2, P.binsA), P.W2, P.bitsC, 255);
+        scan_matrix(a, (uint64_t)P.binsA * kBins * P.W2, st);
+        if (aux)
+            scatter<true>(a, a.k1, a.v1, a.a1, a.offA, dim3(P.W2, P.binsA), P.W2, P.bitsC, 255, a.k2, a.v2, a.a2, st);
+        else
+            scatter<false>(a, a.k1, a.v1, nullptr, a.offA, dim3(P.W2, P.binsA), P.W2, P.bitsC, 255, a.k2, a.v2,
+                           a.a2, st);
+        hipLaunchKernelGGL(k_extract_offsets, (P.binsAB + 256) / 256, 256, 0, st, a.off, P.W2, 8u, P.binsAB, n,
+                           a.offAB);
+        const uint32_t maskC = (1u << P.bitsC) - 1;
+        count(a.k2, a.offAB, dim3(P.W3, P.binsAB), P.W3, 0, maskC);
+        scan_matrix(a, (uint64_t)P.binsAB * kBins * P.W3, st);
+        if (aux)
+            scatter<true>(a, a.k2, a.v2, a.a2, a.offAB, dim3(P.W3, P.binsAB), P.W3, 0, maskC, a.k1, a.v1, a.a1, st);
+        else
+            scatter<false>(a, a.k2, a.v2, nullptr, a.offAB, dim3(P.W3, P.binsAB), P.W3, 0, maskC, a.k1, a.v1,
+                           nullptr, st);
+        hipLaunchKernelGGL(k_extract_offsets, (P.Q + 256) / 256, 256, 0, st, a.off, P.W3, P.bitsC, P.Q, n, a.offQ);
+        o.keys = a.k1;
+        o.vals = a.v1;
+        o.aux = a.a1;
         o.aux_is_pos = aux ? 0 : 1;
     }
     FKS_TIMED("fks_part_sizes", st,

@@ -26,14 +26,18 @@ struct WideSeg {
     uint32_t c;          // space factor: the attempt fails when the map's cells exceed c*n
 };
 
+// Radix passes over the partition index q (bits_q bits), at most 8 bits (256 bins) each:
+// one pass up to 2^8 partitions, two up to 2^16, three beyond (n < 2^30 gives q < 2^20).
 struct PartPlan {
     uint32_t Q;        // partitions
     uint32_t bits_q;   // ceil(log2 Q)
-    uint32_t passes;   // scatter passes: 0, 1 or 2
+    uint32_t passes;   // scatter passes: 0, 1, 2 or 3
     uint32_t shiftA;   // first-level bin = q >> shiftA
     uint32_t binsA;    // first-level bins
-    uint32_t bitsB;    // second-level bin = q & (2^bitsB - 1)
-    uint32_t W1, W2;   // workers of the first pass / per first-level bin in the second pass
+    uint32_t bitsB;    // two passes: second-level bin = q & (2^bitsB - 1); three: (q >> bitsC) & 255
+    uint32_t binsAB;   // three passes: bins after the second pass (q >> bitsC)
+    uint32_t bitsC;    // three passes: third-level bin = q & (2^bitsC - 1)
+    uint32_t W1, W2, W3;   // workers of the first pass / per bin of the second and third passes
     uint64_t matrix;   // entries of the largest count matrix
 };
 
@@ -56,6 +60,7 @@ struct PartArgs {
     uint32_t* tsum;             // scan tile sums
     uint64_t* tpre;             // scanned tile sums
     uint64_t* offA;             // 257 first-level bin offsets
+    uint64_t* offAB;            // three passes: binsAB+1 second-level bin offsets
     uint64_t* offQ;             // Q+1 partition offsets
     uint32_t* sqQ;              // Q sums of squared sizes
     uint64_t* cbase;            // Q+1 cell bases

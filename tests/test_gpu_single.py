@@ -178,6 +178,27 @@ def test_bench_size_bit_exact():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n", [(1 << 26) + 1, (1 << 27) + 12345])
+def test_three_radix_passes_bit_exact(n):
+    """More than 2^16 partitions of 1024 buckets: the partition index is grouped in three
+    radix passes of at most 8 bits each (2^26 + 1 keys is the smallest such build).  The
+    table equals the oracle's byte for byte; sampled lookups equal the oracle's."""
+    seed = 0x3A55 + n
+    announce(f"gpu single u64: three radix passes, n={n}")
+    keys = workloads.unique_u64(n, n + 5, dense_fraction=0.25)
+    vals = np.arange(n, dtype=np.uint32)
+    m = gpu_build(keys, vals, seed)
+    ref = oracle.build_u64(keys, vals, seed)
+    assert_same_table(m, ref)
+    rng = np.random.default_rng(n)
+    q = np.concatenate([keys[rng.integers(0, n, size=50000)],
+                        rng.integers(0, 2**64, size=50000, dtype=np.uint64, endpoint=False)])
+    v, f = gpu_lookup(m, q)
+    rv, rf = ref.lookup(q, missing=MISSING)
+    assert (f == rf).all() and (v == rv).all()
+    del m, ref
+
+
 # ---- attempts with unusual bucket sizes ------------------------------------------------
 
 def skewed_keys(n, seed, per_bucket, rng_seed, big=0):
