@@ -180,6 +180,67 @@ def extra_strings(dev, reps=5):
             "context_bytes": int(data.size), "answers_checked": ok}
 
 
+# Table 1 of the paper (one A100, Futhark, n = 10^7, every inserted key queried), ms
+PAPER_TABLE1_MS = {"u64": {"build": 18.3, "lookup": 3.3, "member": 1.6},
+                   "strings": {"build": 33.2, "lookup": 4.3, "member": 2.8}}
+
+
+def extra_paper_shape(dev, reps=5):
+    """The workload shape of the paper's Table 1 (Section 4): 10^7 unique uniform uint64 keys and
+    10^7 unique strings of 5..25 lowercase bytes, uint32 values; lookup and membership of every
+    inserted key (100 % hits), in shuffled order.  The paper's A100 times are given beside ours
+    as context (other hardware)."""
+    import torch
+    from paper_2508_11443_amd import fks, workloads
+    n = 10 ** 7
+    st = torch.cuda.current_stream()
+    rng = np.random.default_rng(1010)
+    res = {"config": "10^7 unique keys, uint32 values = index; every key looked up once, shuffled"}
+    keys = workloads.unique_u64(n, 1011, dense_fraction=0.0)
+    perm = rng.permutation(n)
+    d_keys = torch.from_numpy(keys.view(np.int64)).to(dev)
+    d_vals = torch.arange(n, dtype=torch.int32, device=dev)
+    d_q = torch.from_numpy(keys[perm].view(np.int64)).to(dev)
+    v = torch.empty(n, dtype=torch.int32, device=dev)
+    f = torch.empty(n, dtype=torch.uint8, device=dev)
+    fks.fks_build_u64(d_keys, d_vals, 7, stream=st).destroy()
+    tb = _median_ms(lambda: fks.fks_build_u64(d_keys, d_vals, 7, stream=st), reps, st)
+    m = fks.fks_build_u64(d_keys, d_vals, 7, stream=st)
+    tl = _median_ms(lambda: fks.fks_lookup_u64(m, d_q, v, f, stream=st), reps, st)
+    ok = bool(f.all()) and bool(torch.equal(v.cpu(), torch.from_numpy(perm.astype(np.int32))))
+    tm = _median_ms(lambda: fks.fks_contains_u64(m, d_q, f, stream=st), reps, st)
+    ok = ok and bool(f.all())
+    m.destroy()
+    res["u64"] = {"build_ms": round(tb, 4), "lookup_ms": round(tl, 4), "member_ms": round(tm, 4),
+                  "answers_checked": ok}
+    del d_keys, d_vals, d_q
+    off, data = workloads.random_strings(n, 1012, min_len=5, max_len=25)
+    lens = off[1:] - off[:-1]
+    qoff = np.zeros(n + 1, np.int64)
+    np.cumsum(lens[perm], out=qoff[1:])
+    qdata = data[np.repeat(off[perm] - qoff[:-1], lens[perm]) + np.arange(qoff[-1])]
+    d_off = torch.from_numpy(off).to(dev)
+    d_data = torch.from_numpy(data).to(dev)
+    d_vals = torch.arange(n, dtype=torch.int32, device=dev)
+    d_qo = torch.from_numpy(qoff).to(dev)
+    d_qd = torch.from_numpy(qdata).to(dev)
+    fks.fks_build_bytes(d_off, d_data, d_vals, 7, stream=st).destroy()
+    tb = _median_ms(lambda: fks.fks_build_bytes(d_off, d_data, d_vals, 7, stream=st), reps, st)
+    m = fks.fks_build_bytes(d_off, d_data, d_vals, 7, stream=st)
+    tl = _median_ms(lambda: fks.fks_lookup_bytes(m, d_qo, d_qd, v, f, stream=st), reps, st)
+    ok = bool(f.all()) and bool(torch.equal(v.cpu(), torch.from_numpy(perm.astype(np.int32))))
+    tm = _median_ms(lambda: fks.fks_contains_bytes(m, d_qo, d_qd, f, stream=st), reps, st)
+    ok = ok and bool(f.all())
+    m.destroy()
+    res["strings"] = {"build_ms": round(tb, 4), "lookup_ms": round(tl, 4), "member_ms": round(tm, 4),
+                      "answers_checked": ok}
+    res["paper_a100_ms"] = PAPER_TABLE1_MS
+    res["speedup_over_paper_a100"] = {
+        kind: {op: round(PAPER_TABLE1_MS[kind][op] / res[kind][op + "_ms"], 1) for op in ("build", "lookup", "member")}
+        for kind in ("u64", "strings")}
+    return res
+
+
 def extra_batch(dev, reps=5):
     """Config 4: 4096 maps (log-uniform 16..2^16 keys) in one persistent launch, then 2^24
     needles (75% hits) over them; against the same maps built and queried one map per call."""
@@ -445,6 +506,8 @@ def main():
         torch.cuda.empty_cache()
         log("extra: strings")
         out["strings"] = extra_strings(dev)
+        log("extra: the workload shape of the paper's Table 1")
+        out["paper_table1_shape"] = extra_paper_shape(dev)
         log("extra: batched build")
         out["batched"] = extra_batch(dev)
         log("extra: serving")
