@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -33,6 +34,11 @@ struct Ctrl {
     uint64_t S;
     uint32_t oversize, bad_input, exhausted, dup, max_t, pad;   // same layout as Readback
 };
+static_assert(sizeof(Ctrl) == sizeof(Readback), "read back as one block");
+// the final pass reads its two reject words from &oversize
+static_assert(offsetof(Ctrl, bad_input) == offsetof(Ctrl, oversize) + sizeof(uint32_t), "adjacent reject words");
+// the final pass updates three outcome words from &exhausted
+static_assert(offsetof(Ctrl, max_t) == offsetof(Ctrl, exhausted) + 2 * sizeof(uint32_t), "adjacent outcome words");
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
