@@ -1,18 +1,18 @@
 // Partitioned construction: the level-one attempt as a few streaming passes.
 //
 // Buckets are cut into partitions of 1024 consecutive buckets (q = j >> 10).
-// Keys are moved into partition order by one or two coalescing scatter passes
-// (at most 256 bins per pass, so every 4096-key tile writes runs of about 16
-// records per bin), then every partition is finished by one workgroup that
-// holds its ~1024 keys in LDS: histogram with LDS atomics (the ranks come with
-// it), scan of the 128 group statistics, grouping, the per-bucket level-two
-// search of make_2, and the coalesced write of the partition's contiguous cells
-// and group headers.  Only the partition totals of squared sizes (the offsets
-// of Section 2.2, at partition granularity) cross partitions: one small pass
-// computes them, one single-block scan turns them into cell bases and the
-// table size S.  Device-scope atomics are used only on a few hundred to a few
-// tens of thousands of counters, once per tile and bin; every per-key access
-// is a coalesced stream or LDS.
+// Keys are moved into partition order by one to three coalescing radix passes
+// over q (at most 8 bits, 256 bins, per pass, so every 8192-record tile writes
+// runs of about 32 records per bin; every worker's offsets come from a scanned
+// count matrix), then every partition is finished by one workgroup that holds
+// its ~1024 keys in LDS: ranks from an LDS histogram, scan of the 128 group
+// statistics, grouping, the per-bucket level-two search of make_2, and the
+// coalesced write of the partition's contiguous cells and group headers.  Only
+// the partition totals of squared sizes (the offsets of Section 2.2, at
+// partition granularity) cross partitions: one small pass computes them, a scan
+// turns them into cell bases and the table size S.  Device-scope atomics are
+// used only to raise an attempt's outcome flags; every per-key access is a
+// coalesced stream or LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,10 +26,9 @@ namespace fks {
 constexpr uint32_t kPB = 256;                 // threads per block, partition passes
 constexpr uint32_t kPItems = 16;              // keys per thread per tile
 constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
-// keys per thread per scatter tile: 8192-key tiles write runs of ~32 records per bin (one
-// workgroup per CU); with an aux word the records are larger and the tile stays at 4096 keys
-// scatter tiles of the single-map passes: 1024 threads x 8 records (8192 records, 101 KB of
-// LDS, one block and four waves per SIMD on a CU), or x 4 when an aux word travels
+// scatter tiles of the single-map passes: 1024 threads x 8 records (8192 records, runs of ~32
+// per bin, 101 KB of LDS: one workgroup and four waves per SIMD on a CU), or x 4 when an aux
+// word travels (larger records, 4096-record tiles)
 constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 8, kPScatterItemsAux = 4;
 constexpr uint32_t kBins = 256;               // bins per scatter pass
 constexpr uint32_t kFinalKeyCap = 1280;       // keys of one partition held in LDS (mean 1024, sd 32)
@@ -441,8 +440,6 @@ struct FinalLds {
     uint32_t flags[3];   // exhausted, dup, max_t
 };
 
-// smallest trial for a bucket of 2..8 keys held in registers: one 64-bit
-// occupancy mask, remainders by multiplication
 // largest of a small value (below 16) over the wave's active lanes
 __device__ __forceinline__ uint32_t wave_max16(uint32_t v) {
     uint32_t m = 0;
@@ -454,8 +451,9 @@ __device__ __forceinline__ uint32_t wave_max16(uint32_t v) {
     return m;
 }
 
-// smax: the largest bucket among the wave's active lanes; key slots beyond it are
-// skipped by the whole wave
+// smallest trial from t0 on for a bucket of 2..8 keys held in registers: one 64-bit
+// occupancy mask, remainders by multiplication.  smax: the largest bucket among the
+// wave's active lanes; key slots beyond it are skipped by the whole wave
 __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T, uint32_t s, const uint64_t (&kx)[8],
                                                     uint64_t M, uint32_t t0 = 0, uint32_t smax = 8) {
     const uint32_t s2 = s * s;
