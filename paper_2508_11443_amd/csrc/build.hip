@@ -262,7 +262,11 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         if ((rc = part_prepare(a, st, o))) break;
         // the attempt's level-two triples travel while the passes run
         for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
-        FKS_HIP(hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st));
+        if (hipError_t e = hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st);
+            e != hipSuccess) {
+            rc = hip_fail(e);
+            break;
+        }
         if (direct) {
             // the final pass follows the size pass without a host round trip; the host waits
             // once per attempt, for the outcome
@@ -310,8 +314,7 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             release();
             return FKS_OK;
         }
-        FKS_HIP(hipMemcpyAsync(host, ctrl, sizeof(Readback), hipMemcpyDeviceToHost, st));
-        FKS_HIP(hipStreamSynchronize(st));
+        if ((rc = readback())) break;
         if (host->bad_input) {
             rc = FKS_EINVAL;
             break;
@@ -408,8 +411,9 @@ static int build_common(fks_map* M, const uint64_t* d_keys_in, const uint32_t* d
         M->ctx_nbytes = nbytes;
         M->device_bytes += 8 * (n + 1) + nbytes;
         // the offsets are checked by the fingerprint pass, before any byte is read through them
-        FKS_HIP(hipMemcpyAsync(M->ctx_off, d_off, 8 * (n + 1), hipMemcpyDeviceToDevice, st));
-        if (nbytes) FKS_HIP(hipMemcpyAsync(M->ctx_bytes, d_bytes, nbytes, hipMemcpyDeviceToDevice, st));
+        hipError_t e = hipMemcpyAsync(M->ctx_off, d_off, 8 * (n + 1), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && nbytes) e = hipMemcpyAsync(M->ctx_bytes, d_bytes, nbytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail(hip_fail(e));
     }
 
     M->magic_n = fastmod_magic((uint32_t)n);

@@ -52,30 +52,33 @@ extern "C" int fks_probe_random_reads(uint64_t buffer_bytes, uint64_t probes, ui
         dev_free(sink, st);
         return FKS_ENOMEM;
     }
-    hipEvent_t a, b;
-    FKS_HIP(hipEventCreate(&a));
-    FKS_HIP(hipEventCreate(&b));
-    FKS_HIP(hipMemsetAsync(buf, 1, blocks * width_bytes, st));
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipMemsetAsync(buf, 1, blocks * width_bytes, st);
     const uint64_t mask = blocks - 1;
     const unsigned grid = 16384;
-    for (int rep = 0; rep < 2; ++rep) {   // the first pass warms the translation caches
-        FKS_HIP(hipEventRecord(a, st));
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the first pass warms the translation caches
+        e = hipEventRecord(a, st);
+        if (e != hipSuccess) break;
         switch (width_bytes) {
             case 16: hipLaunchKernelGGL(k_probe_random<1>, grid, 256, 0, st, buf, mask, probes, sink); break;
             case 32: hipLaunchKernelGGL(k_probe_random<2>, grid, 256, 0, st, buf, mask, probes, sink); break;
             case 64: hipLaunchKernelGGL(k_probe_random<4>, grid, 256, 0, st, buf, mask, probes, sink); break;
             default: hipLaunchKernelGGL(k_probe_random<8>, grid, 256, 0, st, buf, mask, probes, sink); break;
         }
-        FKS_HIP(hipEventRecord(b, st));
+        e = hipEventRecord(b, st);
     }
-    FKS_HIP(hipEventSynchronize(b));
+    if (e == hipSuccess) e = hipEventSynchronize(b);
     float ms = 0.f;
-    FKS_HIP(hipEventElapsedTime(&ms, a, b));
-    *ms_out = ms;
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e == hipSuccess) *ms_out = ms;
+    // released on every path; the frees are ordered after the probe on the stream
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     dev_free(buf, st);
     dev_free(sink, st);
-    FKS_HIP(hipStreamSynchronize(st));
-    return FKS_OK;
+    const hipError_t e2 = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
