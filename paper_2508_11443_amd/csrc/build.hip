@@ -3,7 +3,7 @@
 //
 // One attempt r runs the partition passes of partition.hip on the stream:
 // every key's bucket g k = hash(A_r) k mod n (make_1, Section 2.3) decides its
-// partition of 1024 consecutive buckets; one or two radix passes group the
+// partition of 1024 consecutive buckets; one to three radix passes group the
 // records by partition; a per-partition histogram gives the bucket sizes and
 // the partition's sum of squared sizes, and their exclusive scan the table size
 // S = sum s^2 (the offsets of Section 2.2); then one workgroup per partition
