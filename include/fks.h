@@ -178,11 +178,17 @@ int fks_lookup_u64_v64(const fks_map* map, const uint64_t* d_queries, uint64_t m
  * needle's context differs from the map's): needle i is bytes
  * [d_q_offsets[i], d_q_offsets[i+1]) of d_q_bytes.  A hit needs equal
  * fingerprints and then equal bytes (a third read, of the stored string).
+ * The needle offsets (m+1 int64) are the caller's contract and are not
+ * checked (the call has no size for d_q_bytes): they must be non-decreasing,
+ * start at or above 0 and stay inside d_q_bytes.  Either output may be NULL.
+ * Errors: FKS_EINVAL (NULL map or needle arrays with m > 0, a map that is not
+ * a string map), FKS_EHIP.
  */
 int fks_lookup_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
                      uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
                      void* stream);
 
+/* Membership only for string needles, under the same contract. */
 int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
                        uint64_t m, uint8_t* d_found_out, void* stream);
 
@@ -316,7 +322,9 @@ void fks_server_destroy(fks_server* srv);
  * Times `probes` independent random reads of width_bytes (16, 32, 64 or 128)
  * from a buffer of about buffer_bytes (allocated and released inside), after
  * one warm-up pass; *ms_out receives the time of the second pass.  The rate
- * probes / time is the ceiling that one- and two-probe lookups run against. */
+ * probes / time is the ceiling that one- and two-probe lookups run against.
+ * Synchronous.  Errors: FKS_EINVAL (ms_out NULL, probes 0, another width),
+ * FKS_ENOMEM, FKS_EHIP; the buffers are released on every path. */
 int fks_probe_random_reads(uint64_t buffer_bytes, uint64_t probes, uint32_t width_bytes, void* stream,
                            double* ms_out);
 
