@@ -192,6 +192,44 @@ int fks_lookup_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8
 int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
                        uint64_t m, uint8_t* d_found_out, void* stream);
 
+/* ---- map and reduce over values -------------------------------------------
+ * Section 1 names the operations a hash map shares with an array: mapping a
+ * function over its values, and reducing its values to one value.
+ *
+ * fks_map_values: a new map (release with fks_destroy) with the keys of `map`
+ * and the value op(v) for each key's value v.  The header, the level-two
+ * triples and a string map's context are copied unchanged and every cell's
+ * value is rewritten, so the new table is byte for byte the one that building
+ * the pairs (k, op(v)) with the same seed and parameters writes.  Arithmetic is
+ * modulo 2^32 for maps with 32-bit values (a and b are taken modulo 2^32) and
+ * modulo 2^64 for maps of fks_build_u64_v64.  FKS_VOP_GATHER reads
+ * d_table[v] (table_len device entries of the value width: uint32, or uint64
+ * for fks_build_u64_v64 maps); a value v >= table_len fails the call with
+ * FKS_EINVAL and no map.  `map` is not modified.  Synchronises the stream
+ * once.  Errors: FKS_EINVAL (NULL map/out, unknown op, NULL table with
+ * table_len > 0, a value outside the table), FKS_ENOMEM, FKS_EHIP.
+ *
+ * fks_reduce_values: *d_out (one uint64 on the device) = the fold of op over
+ * the values of the map's n keys, each key counted once (the fill copies of a
+ * bucket's lowest key are not values of the map).  FKS_VRED_SUM is the sum
+ * modulo 2^64; on an empty map the result is the operation's identity (0 for
+ * SUM, MAX and XOR; all ones of the value width for MIN).  Asynchronous on
+ * `stream`.  Errors: FKS_EINVAL (NULL map/d_out, unknown op), FKS_ENOMEM,
+ * FKS_EHIP.                                                                  */
+#define FKS_VOP_ADD    0u   /* v + a */
+#define FKS_VOP_MUL    1u   /* v * a */
+#define FKS_VOP_XOR    2u   /* v ^ a */
+#define FKS_VOP_AFFINE 3u   /* v * a + b */
+#define FKS_VOP_GATHER 4u   /* d_table[v] */
+#define FKS_VRED_SUM   0u
+#define FKS_VRED_MIN   1u
+#define FKS_VRED_MAX   2u
+#define FKS_VRED_XOR   3u
+
+int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint64_t b, const void* d_table,
+                   uint64_t table_len, void* stream, fks_map** out);
+int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream);
+
 /* Sizes and build outcome of a map. */
 int fks_info(const fks_map* map, fks_map_info* info);
 

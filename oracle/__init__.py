@@ -17,6 +17,8 @@ Modules:
                       numpy, written from the paper's data-parallel vocabulary
                       (Figure 1), to show it picks the same level-two
                       constants as the per-bucket make_2.
+  ``values``       -- mapping a function over a map's values and reducing them
+                      (Section 1), by their plain definitions over the pairs.
 """
 from .cbind import (OracleMap, build_u64, build_u64_v64, build_u64_dedup, build_bytes, liboracle, ensure_built,
                     splitmix, hash32, fingerprint, level1_consts, level2_consts,

@@ -1,0 +1,233 @@
+// Map and reduce over the values of a built map (Section 1: like an array, a
+// hash map lets one map a function over its values or reduce them to a single
+// value).
+//
+// A map's table is fixed by its keys, seed and parameters; the values only ride
+// in the cells.  Mapping f over the values keeps the group headers, the
+// level-two triples and every key word, and rewrites the value of every cell,
+// the copies written by the fill rule of Section 2.2 included, so that the new
+// table is byte for byte the one a build over the pairs (k, f(v)) writes.
+// A reduction visits every key once: a cell holds its own key when the key's
+// level-two hash lands on it, while a fill copy of a bucket's lowest key sits
+// in a cell that key does not hash to and is skipped.  Both passes stream the
+// table in address order.
+#include <hip/hip_runtime.h>
+
+#include "fks_internal.hpp"
+#include "prof.hpp"
+
+namespace fks {
+
+constexpr int kVBlock = 256;
+constexpr uint32_t kVPartials = 1024;   // most workgroups of the reduction's first pass
+
+__device__ __forceinline__ uint64_t cell_value(const Cell& c, bool v64) {
+    return v64 ? ((uint64_t)c.aux << 32) | c.val : (uint64_t)c.val;
+}
+
+// v -> f(v) for one of the FKS_VOP_* operations, in the map's value width;
+// a gather index outside the table sets `bad` and yields 0
+template <bool V64>
+__device__ __forceinline__ uint64_t apply_vop(uint32_t op, uint64_t v, uint64_t a, uint64_t b, const void* table,
+                                              uint64_t len, bool& bad) {
+    uint64_t r;
+    switch (op) {
+        case FKS_VOP_ADD: r = v + a; break;
+        case FKS_VOP_MUL: r = v * a; break;
+        case FKS_VOP_XOR: r = v ^ a; break;
+        case FKS_VOP_AFFINE: r = v * a + b; break;
+        default:
+            if (v < len) {
+                r = V64 ? ((const uint64_t*)table)[v] : (uint64_t)((const uint32_t*)table)[v];
+            } else {
+                bad = true;
+                r = 0;
+            }
+    }
+    return V64 ? r : (uint64_t)(uint32_t)r;
+}
+
+__device__ __forceinline__ uint64_t combine(uint32_t op, uint64_t x, uint64_t y) {
+    switch (op) {
+        case FKS_VRED_SUM: return x + y;
+        case FKS_VRED_MIN: return x < y ? x : y;
+        case FKS_VRED_MAX: return x > y ? x : y;
+        default: return x ^ y;
+    }
+}
+
+// one cell per lane; every cell's value word(s) rewritten, key and aux kept
+template <bool V64>
+__global__ __launch_bounds__(kVBlock) void k_map_values(const Cell* __restrict__ in, Cell* __restrict__ out,
+                                                          uint64_t S, uint32_t op, uint64_t a, uint64_t b,
+                                                          const void* __restrict__ table, uint64_t len,
+                                                          uint32_t* __restrict__ bad_flag) {
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        Cell c = in[i];
+        const uint64_t v = apply_vop<V64>(op, cell_value(c, V64), a, b, table, len, bad);
+        c.val = (uint32_t)v;
+        if (V64) c.aux = (uint32_t)(v >> 32);
+        out[i] = c;
+    }
+    if (bad) atomicOr(bad_flag, 1u);
+}
+
+// block-wide fold of one value per thread (LDS tree); the result in thread 0
+__device__ __forceinline__ uint64_t block_fold(uint64_t v, uint32_t op, uint64_t* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t w = kVBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = combine(op, red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// first pass: one group of eight buckets per lane; each bucket's s^2 cells are
+// tested against the bucket's level-two hash and its own keys folded in
+template <bool V64>
+__global__ __launch_bounds__(kVBlock) void k_reduce_groups(const Group* __restrict__ header,
+                                                             const Cell* __restrict__ slots, uint64_t G, uint64_t S,
+                                                             const Triple* __restrict__ Cg, uint32_t T, uint32_t op,
+                                                             uint64_t ident, uint64_t* __restrict__ partial) {
+    __shared__ Triple C[kTMax];
+    __shared__ uint64_t red[kVBlock];
+    for (uint32_t k = threadIdx.x; k < T; k += kVBlock) C[k] = Cg[k];
+    __syncthreads();
+    uint64_t acc = ident;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const Group h = header[g];
+        for (uint32_t k = 0; k < 8; ++k) {
+            const uint32_t s = nib(h.sizes, k);
+            const uint32_t t = group_t(h, k);
+            if (s == 0 || t >= T) continue;
+            const uint32_t s2 = s * s;
+            const uint64_t start = (uint64_t)h.base + prefix_sq(h.sizes, k);
+            if (start + s2 > S) continue;
+            const Triple c = C[t];
+            for (uint32_t l = 0; l < s2; ++l) {
+                const Cell x = slots[start + l];
+                if (mshash(c, x.key) % s2 == l) acc = combine(op, acc, cell_value(x, V64));
+            }
+        }
+    }
+    const uint64_t r = block_fold(acc, op, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// second pass: one workgroup folds the partials (none for an empty map)
+__global__ __launch_bounds__(kVBlock) void k_reduce_final(const uint64_t* __restrict__ partial, uint32_t np,
+                                                            uint32_t op, uint64_t ident, uint64_t* __restrict__ out) {
+    __shared__ uint64_t red[kVBlock];
+    uint64_t acc = ident;
+    for (uint32_t i = threadIdx.x; i < np; i += kVBlock) acc = combine(op, acc, partial[i]);
+    const uint64_t r = block_fold(acc, op, red);
+    if (threadIdx.x == 0) out[0] = r;
+}
+
+static void free_map(fks_map* M, hipStream_t st) {
+    dev_free(M->header, st);
+    dev_free(M->slots, st);
+    dev_free(M->C, st);
+    dev_free(M->ctx_off, st);
+    dev_free(M->ctx_bytes, st);
+    delete M;
+}
+
+}  // namespace fks
+
+using namespace fks;
+
+extern "C" int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint64_t b, const void* d_table,
+                              uint64_t table_len, void* stream, fks_map** out) {
+    if (!map || !out || op > FKS_VOP_GATHER) return FKS_EINVAL;
+    if (op == FKS_VOP_GATHER && table_len && !d_table) return FKS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool v64 = map->kind == 2;
+    const uint64_t G = (map->n + 7) / 8;
+    const bool ctx = map->kind == 1 && map->ctx_off && map->ctx_bytes;
+    // the new map: the same keys, attempt and parameters; its own copies of the header, the
+    // triples and a string map's context, and cells with the mapped values
+    fks_map* M = new fks_map(*map);
+    M->header = nullptr;
+    M->slots = nullptr;
+    M->C = nullptr;
+    M->ctx_off = nullptr;
+    M->ctx_bytes = nullptr;
+    bool ok = true;
+    if (G) ok = ok && (M->header = (Group*)dev_alloc(16 * G, st));
+    if (map->S) ok = ok && (M->slots = (Cell*)dev_alloc(16 * map->S, st));
+    ok = ok && (M->C = (Triple*)dev_alloc(sizeof(Triple) * map->T, st));
+    if (ctx) {
+        ok = ok && (M->ctx_off = (int64_t*)dev_alloc(8 * (map->n + 1), st));
+        ok = ok && (M->ctx_bytes = (uint8_t*)dev_alloc(map->ctx_nbytes ? map->ctx_nbytes : 1, st));
+    }
+    uint32_t* flag = ok ? (uint32_t*)dev_alloc(64, st) : nullptr;
+    if (!ok || !flag) {
+        dev_free(flag, st);
+        free_map(M, st);
+        return FKS_ENOMEM;
+    }
+    hipError_t e = hipMemsetAsync(flag, 0, 4, st);
+    if (e == hipSuccess && G) e = hipMemcpyAsync(M->header, map->header, 16 * G, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(M->C, map->C, sizeof(Triple) * map->T, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && ctx)
+        e = hipMemcpyAsync(M->ctx_off, map->ctx_off, 8 * (map->n + 1), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && ctx && map->ctx_nbytes)
+        e = hipMemcpyAsync(M->ctx_bytes, map->ctx_bytes, map->ctx_nbytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && map->S) {
+        uint64_t grid = (map->S + kVBlock - 1) / kVBlock;
+        if (grid > 65536) grid = 65536;
+        if (v64)
+            FKS_TIMED("fks_map_values", st,
+                      hipLaunchKernelGGL(k_map_values<true>, (unsigned)grid, kVBlock, 0, st, map->slots, M->slots,
+                                         map->S, op, a, b, d_table, table_len, flag));
+        else
+            FKS_TIMED("fks_map_values", st,
+                      hipLaunchKernelGGL(k_map_values<false>, (unsigned)grid, kVBlock, 0, st, map->slots, M->slots,
+                                         map->S, op, a, b, d_table, table_len, flag));
+        e = hipGetLastError();
+    }
+    uint32_t bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dev_free(flag, st);
+    if (e != hipSuccess || bad) {
+        free_map(M, st);
+        return e != hipSuccess ? hip_fail(e) : FKS_EINVAL;
+    }
+    *out = M;
+    return FKS_OK;
+}
+
+extern "C" int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream) {
+    if (!map || !d_out || op > FKS_VRED_XOR) return FKS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool v64 = map->kind == 2;
+    // the identity of the operation in the map's value width
+    const uint64_t ident = op == FKS_VRED_MIN ? (v64 ? ~0ull : 0xFFFFFFFFull) : 0ull;
+    const uint64_t G = (map->n + 7) / 8;
+    if (G == 0) {
+        hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, nullptr, 0u, op, ident, d_out);
+    } else {
+        uint64_t np = (G + kVBlock - 1) / kVBlock;
+        if (np > kVPartials) np = kVPartials;
+        uint64_t* partial = (uint64_t*)dev_alloc(8 * np, st);
+        if (!partial) return FKS_ENOMEM;
+        if (v64)
+            FKS_TIMED("fks_reduce_values", st,
+                      hipLaunchKernelGGL(k_reduce_groups<true>, (unsigned)np, kVBlock, 0, st, map->header, map->slots,
+                                         G, map->S, map->C, map->T, op, ident, partial));
+        else
+            FKS_TIMED("fks_reduce_values", st,
+                      hipLaunchKernelGGL(k_reduce_groups<false>, (unsigned)np, kVBlock, 0, st, map->header,
+                                         map->slots, G, map->S, map->C, map->T, op, ident, partial));
+        hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, partial, (uint32_t)np, op, ident, d_out);
+        dev_free(partial, st);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libfks.so")
 
 FKS_OK, FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY, FKS_EBUILD, FKS_EHIP = 0, -1, -2, -3, -4, -5
 FKS_LAYOUT_SORTED, FKS_LAYOUT_EYTZINGER = 0, 1
+FKS_VOP_ADD, FKS_VOP_MUL, FKS_VOP_XOR, FKS_VOP_AFFINE, FKS_VOP_GATHER = 0, 1, 2, 3, 4
+FKS_VRED_SUM, FKS_VRED_MIN, FKS_VRED_MAX, FKS_VRED_XOR = 0, 1, 2, 3
 
 
 class FksError(RuntimeError):
@@ -61,6 +63,8 @@ SIGNATURES = [
     ("fks_lookup_bytes", _I32, [_VP, _VP, _VP, _U64, _VP, _VP, _U32, _VP]),
     ("fks_contains_bytes", _I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
     ("fks_info", _I32, [_VP, _VP]),
+    ("fks_map_values", _I32, [_VP, _U32, _U64, _U64, _VP, _U64, _VP, ctypes.POINTER(_VP)]),
+    ("fks_reduce_values", _I32, [_VP, _U32, _VP, _VP]),
     ("fks_export", _I32, [_VP, _VP, _VP, _VP]),
     ("fks_destroy", None, [_VP]),
     ("fks_strerror", ctypes.c_char_p, [_I32]),
@@ -232,6 +236,38 @@ def fks_build_u64_v64(keys, vals, seed: int, c=None, T=None, R=None, stream=None
                                    seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
     _check(rc, "fks_build_u64_v64")
     return FksMap(out.value, "u64v64")
+
+
+def fks_map_values(m: FksMap, op: int, a: int = 0, b: int = 0, table=None, stream=None) -> FksMap:
+    """A new map with the keys of m and op(v) as values (FKS_VOP_*); table: the device tensor
+    FKS_VOP_GATHER reads (uint32 entries, or 64-bit for maps with 64-bit values)."""
+    if table is not None:
+        kinds = _u64_types() if m.kind == "u64v64" else _u32_types()
+        d_table, n_table = _dev(table, kinds, "table"), table.numel()
+    else:
+        d_table, n_table = None, 0
+    out = ctypes.c_void_p()
+    mask = (1 << 64) - 1
+    rc = _load().fks_map_values(m.handle, op, a & mask, b & mask, d_table, n_table, _stream(stream),
+                                ctypes.byref(out))
+    _check(rc, "fks_map_values")
+    return FksMap(out.value, m.kind)
+
+
+def fks_reduce_values(m: FksMap, op: int, out=None, stream=None):
+    """Fold of op (FKS_VRED_*) over the map's values, each key once.  With out (a one-element
+    int64/uint64 device tensor) the call is asynchronous and returns out; without it, the
+    result is returned as a Python int."""
+    import torch
+    own = out is None
+    if own:
+        out = torch.empty(1, dtype=torch.int64, device=torch.device("cuda", torch.cuda.current_device()))
+    rc = _load().fks_reduce_values(m.handle, op, _dev(out, _u64_types(), "out"), _stream(stream))
+    _check(rc, "fks_reduce_values")
+    if not own:
+        return out
+    torch.cuda.synchronize()   # the fold may run on a stream other than the current one
+    return int(out.cpu().numpy().view("uint64")[0])
 
 
 def fks_lookup_u64_v64(m: FksMap, queries, vals_out, found_out=None, missing: int = 2**64 - 1, stream=None):
