@@ -153,6 +153,32 @@ def extra_search(d_keys, d_vals, d_q, d_expect, d_v, d_f, stream, hash_build_ms,
     return res
 
 
+def extra_values(d_keys, d_vals, stream, reps=5):
+    """Map and reduce over the values of the benchmark's map (2^26 keys, values = index):
+    fks_map_values with v + 1 (a new map: header and triples copied, every cell rewritten) and
+    fks_reduce_values with the sum (every cell read, each key's own cell folded in)."""
+    import torch
+    from paper_2508_11443_amd import fks
+    n = d_keys.numel()
+    m = fks.fks_build_u64(d_keys, d_vals, SEED, stream=stream)
+    inf = m.info()
+    S, G = inf["S"], (n + 7) // 8
+    tm = _median_ms(lambda: fks.fks_map_values(m, fks.FKS_VOP_ADD, 1, stream=stream), reps, stream)
+    out = torch.empty(1, dtype=torch.int64, device=d_keys.device)
+    tr = _median_ms(lambda: fks.fks_reduce_values(m, fks.FKS_VRED_SUM, out=out, stream=stream), reps, stream)
+    m2 = fks.fks_map_values(m, fks.FKS_VOP_ADD, 1, stream=stream)
+    ok = fks.fks_reduce_values(m, fks.FKS_VRED_SUM, stream=stream) == n * (n - 1) // 2
+    ok = ok and fks.fks_reduce_values(m2, fks.FKS_VRED_SUM, stream=stream) == n * (n - 1) // 2 + n
+    m2.destroy()
+    m.destroy()
+    map_bytes = 2 * 16 * S + 2 * 16 * G     # cells read and written, header copied
+    red_bytes = 16 * S + 16 * G             # cells and header read
+    return {"config": "the map of the main workload (2^26 uint64 keys, values = index)",
+            "map_values_ms": round(tm, 4), "map_values_gbs": round(map_bytes / (tm * 1e-3) / 1e9, 1),
+            "reduce_sum_ms": round(tr, 4), "reduce_gbs": round(red_bytes / (tr * 1e-3) / 1e9, 1),
+            "answers_checked": bool(ok)}
+
+
 def extra_strings(dev, reps=5):
     """Config 3: 2^22 unique lowercase strings (4..64 bytes), 2^22 needles at 50% hits."""
     import torch
@@ -503,6 +529,8 @@ def main():
                                   "same_header_bytes": bool((hr == hb).all())}
         log("extra: comparison maps (sorted array, Eytzinger)")
         out["search_maps"] = extra_search(d_keys, d_vals, d_q, d_expect, d_v, d_f, stream, build_ms, lookup_ms)
+        log("extra: map and reduce over values")
+        out["values"] = extra_values(d_keys, d_vals, stream)
         del d_keys, d_vals, d_q, d_expect, d_v, d_f
         torch.cuda.empty_cache()
         log("extra: strings")
