@@ -74,4 +74,8 @@ def test_host_only_entry_points(lib):
                              ctypes.byref(out)) == fks.FKS_EINVAL
     assert lib.fks_lookup_u64(None, None, 0, None, None, 0, None) == fks.FKS_EINVAL
     assert lib.fks_info(None, None) == fks.FKS_EINVAL
+    assert lib.fks_map_values(None, fks.FKS_VOP_ADD, 1, 0, None, 0, None, ctypes.byref(out)) == fks.FKS_EINVAL
+    assert lib.fks_reduce_values(None, fks.FKS_VRED_SUM, None, None) == fks.FKS_EINVAL
+    assert lib.fks_probe_random_reads(1 << 20, 0, 16, None, None) == fks.FKS_EINVAL
+    assert out.value is None   # out-parameters untouched on failure
     lib.fks_destroy(None)
