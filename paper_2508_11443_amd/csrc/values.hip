@@ -19,7 +19,7 @@
 namespace fks {
 
 constexpr int kVBlock = 256;
-constexpr uint32_t kVPartials = 1024;   // most workgroups of the reduction's first pass
+constexpr uint32_t kVPartials = 65536;  // most workgroups of the reduction's first pass (one group per lane up to 2^27 keys)
 
 __device__ __forceinline__ uint64_t cell_value(const Cell& c, bool v64) {
     return v64 ? ((uint64_t)c.aux << 32) | c.val : (uint64_t)c.val;
