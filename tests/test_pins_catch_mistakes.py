@@ -180,3 +180,57 @@ def test_table_mutants_fail_checks(name):
     keys, vals, sigma, r, h, s = _table()
     h2, s2 = TABLE_MUTANTS[name](h, s, keys.size)
     assert _fails(fkscheck.check_table, keys, vals, sigma, r, h2, s2)
+
+
+# ---- map and reduce over values ------------------------------------------------------
+
+from oracle import values as OV  # noqa: E402
+from tests import test_oracle_values as PV  # noqa: E402
+
+
+def _map_64_always(v, op, a, b, table, width):
+    return OV.map_values(v, op, a, b, table, 64)
+
+
+def _map_affine_swapped(v, op, a, b, table, width):
+    return OV.map_values(v, op, b, a, table, width) if op == OV.VOP_AFFINE else OV.map_values(v, op, a, b, table, width)
+
+
+def _map_affine_no_b(v, op, a, b, table, width):
+    return OV.map_values(v, OV.VOP_MUL, a, 0, table, width) if op == OV.VOP_AFFINE else \
+        OV.map_values(v, op, a, b, table, width)
+
+
+def _map_gather_wraps(v, op, a, b, table, width):
+    if op == OV.VOP_GATHER:
+        t = np.asarray(table)
+        return t[np.asarray(v).astype(np.int64) % t.size]
+    return OV.map_values(v, op, a, b, table, width)
+
+
+MAP_MUTANTS = {
+    "32-bit values kept to 64 bits": _map_64_always,
+    "affine operands swapped": _map_affine_swapped,
+    "affine additive term dropped": _map_affine_no_b,
+    "gather index wrapped instead of refused": _map_gather_wraps,
+}
+
+
+@pytest.mark.parametrize("name", sorted(MAP_MUTANTS))
+def test_map_values_mutants_fail_pins(name):
+    assert _fails(PV.pin_map_values, MAP_MUTANTS[name])
+
+
+REDUCE_MUTANTS = {
+    "min of an empty map is 0": lambda v, op, w: 0 if (op == OV.VRED_MIN and np.asarray(v).size == 0)
+    else OV.reduce_values(v, op, w),
+    "xor folded as or": lambda v, op, w: int(np.bitwise_or.reduce(np.asarray(v).astype(np.uint64)))
+    if (op == OV.VRED_XOR and np.asarray(v).size) else OV.reduce_values(v, op, w),
+    "last value dropped": lambda v, op, w: OV.reduce_values(np.asarray(v)[:-1], op, w),
+    "max folded as min": lambda v, op, w: OV.reduce_values(v, OV.VRED_MIN if op == OV.VRED_MAX else op, w),
+}
+
+
+@pytest.mark.parametrize("name", sorted(REDUCE_MUTANTS))
+def test_reduce_values_mutants_fail_pins(name):
+    assert _fails(PV.pin_reduce_values, REDUCE_MUTANTS[name])
