@@ -145,6 +145,14 @@ def _dev(t, dtypes, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _fits(count: int, **tensors):
+    """Refuse, before any device work, a tensor that holds fewer than `count` entries where the
+    call reads or writes one entry per needle (the kernels index it up to count)."""
+    for name, t in tensors.items():
+        if t is not None and t.numel() < count:
+            raise ValueError(f"{name} holds {t.numel()} entries; the call touches {count}")
+
+
 def _u64_types():
     import torch
     return (torch.int64, torch.uint64)
@@ -259,6 +267,7 @@ def fks_reduce_values(m: FksMap, op: int, out=None, stream=None):
     int64/uint64 device tensor) the call is asynchronous and returns out; without it, the
     result is returned as a Python int."""
     import torch
+    _fits(1, out=out)
     own = out is None
     if own:
         out = torch.empty(1, dtype=torch.int64, device=torch.device("cuda", torch.cuda.current_device()))
@@ -272,6 +281,7 @@ def fks_reduce_values(m: FksMap, op: int, out=None, stream=None):
 
 def fks_lookup_u64_v64(m: FksMap, queries, vals_out, found_out=None, missing: int = 2**64 - 1, stream=None):
     import torch
+    _fits(queries.numel(), vals_out=vals_out, found_out=found_out)
     rc = _load().fks_lookup_u64_v64(m.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
                                     _dev(vals_out, _u64_types(), "vals_out"),
                                     _dev(found_out, (torch.uint8, torch.bool), "found_out"),
@@ -298,6 +308,7 @@ def fks_build_bytes(offsets, data, vals, seed: int, c=None, T=None, R=None, stre
 
 def fks_lookup_u64(m: FksMap, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):
     import torch
+    _fits(queries.numel(), vals_out=vals_out, found_out=found_out)
     rc = _load().fks_lookup_u64(m.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
                                 _dev(vals_out, _u32_types(), "vals_out"),
                                 _dev(found_out, (torch.uint8, torch.bool), "found_out"),
@@ -307,6 +318,7 @@ def fks_lookup_u64(m: FksMap, queries, vals_out, found_out, missing: int = 0xFFF
 
 def fks_contains_u64(m: FksMap, queries, found_out, stream=None):
     import torch
+    _fits(queries.numel(), found_out=found_out)
     rc = _load().fks_contains_u64(m.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
                                   _dev(found_out, (torch.uint8, torch.bool), "found_out"), _stream(stream))
     _check(rc, "fks_contains_u64")
@@ -315,6 +327,7 @@ def fks_contains_u64(m: FksMap, queries, found_out, stream=None):
 def fks_lookup_bytes(m: FksMap, q_offsets, q_data, vals_out, found_out, missing: int = 0xFFFFFFFF,
                      stream=None):
     import torch
+    _fits(q_offsets.numel() - 1, vals_out=vals_out, found_out=found_out)
     rc = _load().fks_lookup_bytes(m.handle, _dev(q_offsets, (torch.int64,), "q_offsets"),
                                   _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else ctypes.c_void_p(q_offsets.data_ptr()),
                                   q_offsets.numel() - 1, _dev(vals_out, _u32_types(), "vals_out"),
@@ -325,6 +338,7 @@ def fks_lookup_bytes(m: FksMap, q_offsets, q_data, vals_out, found_out, missing:
 
 def fks_contains_bytes(m: FksMap, q_offsets, q_data, found_out, stream=None):
     import torch
+    _fits(q_offsets.numel() - 1, found_out=found_out)
     rc = _load().fks_contains_bytes(m.handle, _dev(q_offsets, (torch.int64,), "q_offsets"),
                                     _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else ctypes.c_void_p(q_offsets.data_ptr()),
                                     q_offsets.numel() - 1, _dev(found_out, (torch.uint8, torch.bool), "found_out"),
@@ -427,6 +441,7 @@ def fks_build_batch_u64(keys, vals, map_offsets, batch_seed: int, c=None, T=None
 def fks_lookup_batch_u64(b: FksBatch, map_ids, queries, vals_out, found_out, missing: int = 0xFFFFFFFF,
                          stream=None):
     import torch
+    _fits(queries.numel(), map_ids=map_ids, vals_out=vals_out, found_out=found_out)
     rc = _load().fks_lookup_batch_u64(b.handle, _dev(map_ids, _u32_types(), "map_ids"),
                                       _dev(queries, _u64_types(), "queries"), queries.numel(),
                                       _dev(vals_out, _u32_types(), "vals_out"),
@@ -501,6 +516,7 @@ class FksServer:
 
     def submit_lookup(self, map_id: int, queries, vals_out, found_out, missing: int = 0xFFFFFFFF):
         import torch
+        _fits(queries.numel(), vals_out=vals_out, found_out=found_out)
         rid = ctypes.c_uint64()
         _check(_load().fks_server_submit_lookup(self._h, map_id, _dev(queries, _u64_types(), "queries"),
                                                 queries.numel(), _dev(vals_out, _u32_types(), "vals_out"),
@@ -603,6 +619,7 @@ def fks_sorted_build_u64(keys, vals, layout: int = FKS_LAYOUT_SORTED, stream=Non
 
 def fks_sorted_lookup_u64(s: FksSorted, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):
     import torch
+    _fits(queries.numel(), vals_out=vals_out, found_out=found_out)
     rc = _load().fks_sorted_lookup_u64(s.handle, _dev(queries, _u64_types(), "queries"), queries.numel(),
                                        _dev(vals_out, _u32_types(), "vals_out"),
                                        _dev(found_out, (torch.uint8, torch.bool), "found_out"),
