@@ -156,7 +156,8 @@ int fks_build_bytes(const int64_t* d_offsets, const uint8_t* d_bytes, uint64_t n
  * lookup (Figure 2) for m integer needles: d_vals_out[i] = value of
  * d_queries[i] and d_found_out[i] = 1 if the key is in the map, else
  * d_vals_out[i] = missing and d_found_out[i] = 0.  At most two dependent
- * table reads per needle.  Either output may be NULL to skip it.
+ * table reads per needle.  Either output may be NULL to skip it; a given
+ * output holds m entries (the call cannot check its size).
  * Errors: FKS_EINVAL (NULL map/queries with m > 0, string map), FKS_EHIP.
  */
 int fks_lookup_u64(const fks_map* map, const uint64_t* d_queries, uint64_t m,
