@@ -82,3 +82,39 @@ def test_reduce_values_pins():
 
 def test_map_values_pins():
     pin_map_values(_oracle_map)
+
+
+def test_own_cells_are_exactly_the_keys():
+    """The reduction's reading, on the oracle's own tables: a cell counts when its key's level-two
+    hash lands on it.  Over a built table those cells are exactly the n keys' cells (every fill copy
+    sits where its key does not hash), so folding over them is folding over the input values."""
+    import oracle
+    from oracle import rounds, spec
+    from paper_2508_11443_amd import workloads
+    from tests import fkscheck
+    for n, seed in [(1, 1), (9, 2), (5000, 3), (100003, 4)]:
+        sigma = 0x51 + n
+        keys = workloads.unique_u64(n, seed, dense_fraction=0.5)
+        vals = np.random.default_rng(seed).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        ref = oracle.build_u64(keys, vals, sigma)
+        header, slots = ref.export()
+        _, sizes_all, t_all = fkscheck.decode_header(header, n)
+        sizes, tv = sizes_all[:n], t_all[:n]
+        sq = sizes * sizes
+        offs, owner = rounds.presum(sq), rounds.repiota(sq)
+        ck, cv, _ = fkscheck.decode_cells(slots)
+        S = ck.size
+        local = np.arange(S) - offs[owner]
+        own = np.zeros(S, bool)
+        for t in np.unique(tv[owner]):
+            sel = tv[owner] == t
+            a0, a1, b = (int(x) for x in spec.level2_consts(sigma, ref.r, int(t)))
+            own[sel] = rounds.hash_vec(a0, a1, b, ck[sel]) % sq[owner[sel]] == local[sel]
+        assert own.sum() == n
+        assert (np.sort(ck[own]) == np.sort(keys)).all()
+        for op in (ov.VRED_SUM, ov.VRED_MIN, ov.VRED_MAX, ov.VRED_XOR):
+            assert ov.reduce_values(cv[own], op) == ov.reduce_values(vals, op)
+        if n >= 5000:
+            # the table holds fill copies, and folding over every cell would count them
+            assert (~own).sum() > 0
+            assert ov.reduce_values(cv, ov.VRED_SUM) != ov.reduce_values(vals, ov.VRED_SUM)
