@@ -403,11 +403,14 @@ def main():
     log(f"generating workload n={n} m={m}")
     keys = workloads.unique_u64(n, DATA_SEED, dense_fraction=0.5)
     vals = np.arange(n, dtype=np.uint32)
-    q, expect = workloads.u64_queries(keys, m, 0.5, DATA_SEED + 1)
+    q, expect, src = workloads.u64_queries(keys, m, 0.5, DATA_SEED + 1, return_index=True)
     d_keys = torch.from_numpy(keys.view(np.int64)).to(dev)
     d_vals = torch.from_numpy(vals.view(np.int32)).to(dev)
     d_q = torch.from_numpy(q.view(np.int64)).to(dev)
     d_expect = torch.from_numpy(expect).to(dev)
+    # the value of a present needle is its key's index (values = index), absent ones get `missing`
+    d_want_v = torch.from_numpy(np.where(src >= 0, src, 0xFFFFFFFF).astype(np.uint32).view(np.int32)).to(dev)
+    del src
     d_v = torch.empty(m, dtype=torch.int32, device=dev)
     d_f = torch.empty(m, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -448,10 +451,9 @@ def main():
     build_ms = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
     lookup_ms = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
 
-    # the answers of the last step are checked before anything is reported
-    ok = bool(torch.equal(d_f, d_expect))
-    hits = d_expect.bool()
-    ok = ok and bool((d_v[~hits] == -1).all())
+    # the answers of the last step are checked before anything is reported: every found
+    # flag, and every value (hits: the key's index; misses: the missing value)
+    ok = bool(torch.equal(d_f, d_expect)) and bool(torch.equal(d_v, d_want_v))
     info = last.info()
     header, _, _ = (None, None, None)
     hb = np.zeros(info["header_bytes"], np.uint8)
@@ -531,7 +533,7 @@ def main():
         out["search_maps"] = extra_search(d_keys, d_vals, d_q, d_expect, d_v, d_f, stream, build_ms, lookup_ms)
         log("extra: map and reduce over values")
         out["values"] = extra_values(d_keys, d_vals, stream)
-        del d_keys, d_vals, d_q, d_expect, d_v, d_f
+        del d_keys, d_vals, d_q, d_expect, d_v, d_f, d_want_v
         torch.cuda.empty_cache()
         log("extra: strings")
         out["strings"] = extra_strings(dev)

@@ -55,8 +55,10 @@ extern "C" {
 #define FKS_ENOMEM   (-2)  /* device allocation failed */
 #define FKS_EDUPKEY  (-3)  /* the no-duplicates contract of from_array_nodup was
                               broken: a bucket that no level-two trial could
-                              separate holds two equal keys */
-#define FKS_EBUILD   (-4)  /* every level-one attempt was rejected */
+                              separate holds two equal keys, or every level-one
+                              attempt was rejected and two keys are equal */
+#define FKS_EBUILD   (-4)  /* every level-one attempt was rejected and the keys
+                              are distinct */
 #define FKS_EHIP     (-5)  /* a HIP runtime call failed; see fks_last_hip_error */
 
 /* ---- parameters ---------------------------------------------------------
@@ -81,6 +83,32 @@ typedef struct fks_params {
 
 typedef struct fks_map fks_map;       /* opaque; owns all of its device memory */
 
+/* ---- device memory ---------------------------------------------------------
+ * Where a build takes its device memory.  The map of Figure 2 owns its arrays
+ * (Section 3.1: it keeps even its own copy of the key context); the caller
+ * decides where they live.
+ *   alloc : returns `bytes` of device memory of the current device, usable in
+ *           stream order on `stream`, or NULL when it cannot.
+ *   free  : releases a pointer that alloc returned, in stream order on
+ *           `stream` (the stream it is called with may differ from the one
+ *           the memory was allocated on only in fks_destroy and the other
+ *           release calls, which pass NULL after the map's last use).
+ *   user  : passed back unchanged.
+ * Every build entry point takes a `const fks_allocator*`: the map (or batch,
+ * or sorted array) and all of the call's scratch come from it, and a failed
+ * alloc makes the call release everything it took and return FKS_ENOMEM
+ * without writing its out-parameter.  The built object keeps a copy of the
+ * struct and returns its memory through it when it is released, so `user`
+ * must stay valid until then.  NULL selects hipMallocAsync / hipFreeAsync on
+ * the device's default memory pool.  Both function pointers must be set
+ * (FKS_EINVAL otherwise).  The library calls them from the thread that made
+ * the entry-point call.                                                       */
+typedef struct fks_allocator {
+    void* (*alloc)(uint64_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, void* stream, void* user);
+    void* user;
+} fks_allocator;
+
 typedef struct fks_map_info {
     uint64_t n;           /* number of keys */
     uint64_t S;           /* number of cells */
@@ -93,6 +121,9 @@ typedef struct fks_map_info {
     uint32_t c, T, R;
     uint32_t max_t;       /* largest trial index used by any bucket */
     uint64_t device_bytes;/* device memory the map holds */
+    uint64_t size_hist[16];/* size_hist[s] = buckets holding s keys (the histogram
+                              of make_1, Section 2.3); sum(s * size_hist[s]) = n,
+                              sum(s^2 * size_hist[s]) = S */
 } fks_map_info;
 
 /* Fill *p with the defaults {4, 64, 16, 0}. */
@@ -108,11 +139,13 @@ void fks_params_default(fks_params* p);
  *            Figure 1); the table is a pure function of (keys as a set,
  *            values, seed, params).
  *   params : NULL for defaults.
+ *   alloc  : where the map and the call's scratch live (see fks_allocator);
+ *            NULL for the device's default stream-ordered pool.
  *   out    : receives the new map (release with fks_destroy).
  * Errors: FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY, FKS_EBUILD, FKS_EHIP.
  */
 int fks_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint64_t seed,
-                  const fks_params* params, void* stream, fks_map** out);
+                  const fks_params* params, const fks_allocator* alloc, void* stream, fks_map** out);
 
 /*
  * from_array (Figure 2) for 64-bit keys: like fks_build_u64, but the u input
@@ -123,7 +156,7 @@ int fks_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, ui
  * Errors: as fks_build_u64 (never FKS_EDUPKEY); u < 2^30.
  */
 int fks_build_u64_from_array(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t u, uint64_t seed,
-                             const fks_params* params, void* stream, fks_map** out);
+                             const fks_params* params, const fks_allocator* alloc, void* stream, fks_map** out);
 
 /*
  * from_array_nodup for 64-bit keys with 64-bit values (the value type of
@@ -135,7 +168,7 @@ int fks_build_u64_from_array(const uint64_t* d_keys, const uint32_t* d_vals, uin
  * FKS_EINVAL).  Errors: as fks_build_u64.
  */
 int fks_build_u64_v64(const uint64_t* d_keys, const uint64_t* d_vals, uint64_t n, uint64_t seed,
-                      const fks_params* params, void* stream, fks_map** out);
+                      const fks_params* params, const fks_allocator* alloc, void* stream, fks_map** out);
 
 /*
  * from_array_nodup for byte-string keys (Section 3.1 contexts, Section 3.3.1
@@ -150,7 +183,7 @@ int fks_build_u64_v64(const uint64_t* d_keys, const uint64_t* d_vals, uint64_t n
  */
 int fks_build_bytes(const int64_t* d_offsets, const uint8_t* d_bytes, uint64_t nbytes,
                     const uint32_t* d_vals, uint64_t n, uint64_t seed,
-                    const fks_params* params, void* stream, fks_map** out);
+                    const fks_params* params, const fks_allocator* alloc, void* stream, fks_map** out);
 
 /*
  * lookup (Figure 2) for m integer needles: d_vals_out[i] = value of
@@ -177,21 +210,21 @@ int fks_lookup_u64_v64(const fks_map* map, const uint64_t* d_queries, uint64_t m
 /*
  * lookup for m string needles given in their own context (Section 3.1: the
  * needle's context differs from the map's): needle i is bytes
- * [d_q_offsets[i], d_q_offsets[i+1]) of d_q_bytes.  A hit needs equal
- * fingerprints and then equal bytes (a third read, of the stored string).
- * The needle offsets (m+1 int64) are the caller's contract and are not
- * checked (the call has no size for d_q_bytes): they must be non-decreasing,
- * start at or above 0 and stay inside d_q_bytes.  Either output may be NULL.
- * Errors: FKS_EINVAL (NULL map or needle arrays with m > 0, a map that is not
- * a string map), FKS_EHIP.
+ * [d_q_offsets[i], d_q_offsets[i+1]) of d_q_bytes, which holds q_nbytes
+ * bytes.  A hit needs equal fingerprints and then equal bytes (a third read,
+ * of the stored string).  A needle whose pair of offsets is not a range
+ * inside d_q_bytes (a negative start, an end before its start, or an end
+ * past q_nbytes) reads nothing and is answered absent.  Either output may be
+ * NULL.  Errors: FKS_EINVAL (NULL map or needle arrays with m > 0, a map that
+ * is not a string map), FKS_EHIP.
  */
 int fks_lookup_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
-                     uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
-                     void* stream);
+                     uint64_t q_nbytes, uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out,
+                     uint32_t missing, void* stream);
 
 /* Membership only for string needles, under the same contract. */
 int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
-                       uint64_t m, uint8_t* d_found_out, void* stream);
+                       uint64_t q_nbytes, uint64_t m, uint8_t* d_found_out, void* stream);
 
 /* ---- map and reduce over values -------------------------------------------
  * Section 1 names the operations a hash map shares with an array: mapping a
@@ -228,10 +261,13 @@ int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uin
 #define FKS_VRED_XOR   3u
 
 int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint64_t b, const void* d_table,
-                   uint64_t table_len, void* stream, fks_map** out);
+                   uint64_t table_len, const fks_allocator* alloc, void* stream, fks_map** out);
 int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream);
 
-/* Sizes and build outcome of a map. */
+
+/* Sizes and build outcome of a map.  The bucket-size histogram is counted by
+   one small kernel over the group headers, on the null stream, which the call
+   waits for.  Errors: FKS_EINVAL, FKS_EHIP. */
 int fks_info(const fks_map* map, fks_map_info* info);
 
 /*
@@ -273,7 +309,7 @@ typedef struct fks_batch fks_batch;
 
 int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_vals, const uint64_t* h_map_offsets,
                         uint32_t M, uint64_t batch_seed, const fks_params* params, uint32_t schedule,
-                        void* stream, fks_batch** out);
+                        const fks_allocator* alloc, void* stream, fks_batch** out);
 
 /* Needle i asks map d_map_ids[i] for key d_queries[i]; map ids >= M are
    answered "absent".  Asynchronous; outputs as fks_lookup_u64. */
@@ -285,7 +321,8 @@ int fks_lookup_batch_u64(const fks_batch* batch, const uint32_t* d_map_ids, cons
    (FKS_OK or an error code), accepted attempt r, cell count S. */
 int fks_batch_status(const fks_batch* batch, int32_t* h_status, uint32_t* h_r, uint32_t* h_S);
 
-/* Sizes of map `index` (returns its status). */
+/* Sizes of map `index` (returns its status), as fks_info reports them; the
+   histogram is counted only for a map that was built (FKS_OK). */
 int fks_batch_info(const fks_batch* batch, uint32_t index, fks_map_info* info);
 
 /* Table of map `index`, laid out as fks_export lays out a single map. */
@@ -338,11 +375,23 @@ typedef struct fks_server_stats {
 
 int fks_server_create(uint64_t budget_bytes, const fks_params* params, uint32_t flags, fks_server** out);
 /* Queue a build; *map_id names the future map at once (lookups may be queued
-   against it before it is built). */
+   against it before it is built).  Ordering: the request's device work starts
+   only after everything queued on `stream` (the submitter's stream, a
+   hipStream_t as void*; NULL = the default stream) before this call, so the
+   inputs may still be in flight there; the call records an event on `stream`
+   and the server's stream waits for it.  A build whose reservation (header +
+   c*n cells + triples) exceeds the whole budget completes at once with
+   FKS_ENOMEM and evicts nothing; otherwise idle maps are evicted, least
+   recently used first, only when that makes room, else the build waits for
+   lookups pinning resident maps to drain. */
 int fks_server_submit_build(fks_server* srv, const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n,
-                            uint64_t seed, uint64_t* req_id, uint32_t* map_id);
+                            uint64_t seed, void* stream, uint64_t* req_id, uint32_t* map_id);
+/* Queue a lookup of m needles against map_id, ordered after `stream` as
+   fks_server_submit_build is.  The outputs are written by the time
+   fks_server_poll reports the request done. */
 int fks_server_submit_lookup(fks_server* srv, uint32_t map_id, const uint64_t* d_queries, uint64_t m,
-                             uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, uint64_t* req_id);
+                             uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, void* stream,
+                             uint64_t* req_id);
 /* *done = 1 once finished; *latency_ms = completion - submission (host clock). */
 int fks_server_poll(fks_server* srv, uint64_t req_id, int* done, int* status, double* latency_ms);
 int fks_server_wait_all(fks_server* srv);
@@ -383,7 +432,7 @@ typedef struct fks_sorted fks_sorted;
    stream once (duplicate check).  Errors: FKS_EINVAL, FKS_ENOMEM, FKS_EDUPKEY,
    FKS_EHIP. */
 int fks_sorted_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint32_t layout,
-                         void* stream, fks_sorted** out);
+                         const fks_allocator* alloc, void* stream, fks_sorted** out);
 /* As fks_lookup_u64: d_vals_out may be NULL (membership only); asynchronous. */
 int fks_sorted_lookup_u64(const fks_sorted* s, const uint64_t* d_queries, uint64_t m, uint32_t* d_vals_out,
                           uint8_t* d_found_out, uint32_t missing_value, void* stream);

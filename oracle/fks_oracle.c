@@ -38,6 +38,10 @@
  *      keys or when sum(s^2) > c*n; make_2 gives up after T trials; a bucket
  *      that gives up and holds two equal keys makes the build fail with the
  *      duplicate-key error, otherwise the level-one attempt is rejected.
+ *      When every attempt is rejected the build fails with the duplicate-key
+ *      error if two of its keys are equal (the precondition of
+ *      from_array_nodup, Section 3.2: equal keys share every bucket and no
+ *      trial separates them), else with the rejected-build error.
  *   R5 an empty cell copies the lowest occupied cell of its own bucket.
  *   R6 strings are fingerprinted by a Horner polynomial over 32-bit
  *      little-endian words modulo the Mersenne prime 2^61-1, seeded with the
@@ -328,6 +332,59 @@ static int or_check_params(uint64_t n, uint32_t c, uint32_t T, uint32_t R)
     return OR_OK;
 }
 
+/* ---- equal keys: the precondition of from_array_nodup (Section 3.2) -----
+ * Plain definition: sort a copy and compare neighbours.  Strings are ordered
+ * by length, then bytes. */
+
+static int or_cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int or_has_equal_u64(const uint64_t* keys, uint64_t n)
+{
+    uint64_t* k = malloc(sizeof(uint64_t) * (n ? n : 1));
+    if (!k) return OR_ENOMEM;
+    memcpy(k, keys, sizeof(uint64_t) * n);
+    qsort(k, n, sizeof(uint64_t), or_cmp_u64);
+    int eq = 0;
+    for (uint64_t i = 1; i < n && !eq; ++i) eq = k[i] == k[i - 1];
+    free(k);
+    return eq;
+}
+
+static const int64_t* or_str_off;
+static const uint8_t* or_str_bytes;
+
+static int or_cmp_str(const void* a, const void* b)
+{
+    uint64_t i = *(const uint64_t*)a, j = *(const uint64_t*)b;
+    int64_t li = or_str_off[i + 1] - or_str_off[i], lj = or_str_off[j + 1] - or_str_off[j];
+    if (li != lj) return li < lj ? -1 : 1;
+    return memcmp(or_str_bytes + or_str_off[i], or_str_bytes + or_str_off[j], (size_t)li);
+}
+
+static int or_has_equal_bytes(const int64_t* off, const uint8_t* bytes, uint64_t n)
+{
+    uint64_t* idx = malloc(sizeof(uint64_t) * (n ? n : 1));
+    if (!idx) return OR_ENOMEM;
+    for (uint64_t i = 0; i < n; ++i) idx[i] = i;
+    or_str_off = off;
+    or_str_bytes = bytes;
+    qsort(idx, n, sizeof(uint64_t), or_cmp_str);
+    int eq = 0;
+    for (uint64_t k = 1; k < n && !eq; ++k) eq = or_cmp_str(&idx[k], &idx[k - 1]) == 0;
+    free(idx);
+    return eq;
+}
+
+/* the error of a build whose every attempt was rejected */
+static int or_rejected(int equal)
+{
+    return equal < 0 ? equal : (equal ? OR_EDUPKEY : OR_EBUILD);
+}
+
 static oracle_map* or_new(int kind, uint64_t n, uint64_t sigma, uint32_t c, uint32_t T, uint32_t R)
 {
     oracle_map* M = calloc(1, sizeof(oracle_map));
@@ -375,7 +432,7 @@ int oracle_build_u64(const uint64_t* keys, const uint32_t* vals, uint64_t n, uin
         if (rc < 0) { oracle_free(M); return rc; }
     }
     oracle_free(M);
-    return OR_EBUILD;
+    return or_rejected(or_has_equal_u64(keys, n));
 }
 
 /* 64-bit values (the paper's value type is polymorphic, Figure 2): the same
@@ -409,7 +466,7 @@ int oracle_build_u64_v64(const uint64_t* keys, const uint64_t* vals, uint64_t n,
     free(lo); free(hi);
     if (rc == OR_OK) { *out = M; return OR_OK; }
     oracle_free(M);
-    return rc < 0 ? rc : OR_EBUILD;
+    return rc < 0 ? rc : or_rejected(or_has_equal_u64(keys, n));
 }
 
 int oracle_build_bytes(const int64_t* offsets, const uint8_t* bytes, const uint32_t* vals,
@@ -450,8 +507,9 @@ int oracle_build_bytes(const int64_t* offsets, const uint8_t* bytes, const uint3
         if (rc < 0) { free(y); oracle_free(M); return rc; }
     }
     free(y);
+    rc = or_rejected(or_has_equal_bytes(M->ctx_off, M->ctx_bytes, n));
     oracle_free(M);
-    return OR_EBUILD;
+    return rc;
 }
 
 /* ---- from_array: the constructor that tolerates duplicate keys ---------

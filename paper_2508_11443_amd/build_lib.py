@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfks.so")
-SOURCES = ["common.cpp", "prof.cpp", "build.hip", "partition.hip", "lookup.hip", "batch.hip", "server.hip", "dedup.hip", "rounds.hip", "probe.hip", "search.hip", "values.hip"]
+SOURCES = ["common.cpp", "prof.cpp", "build.hip", "partition.hip", "lookup.hip", "batch.hip", "server.hip", "dedup.hip", "rounds.hip", "probe.hip", "search.hip", "values.hip", "dupcheck.hip"]
 ARCH = os.environ.get("FKS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

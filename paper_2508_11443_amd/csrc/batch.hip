@@ -577,6 +577,8 @@ struct fks_batch {
     std::vector<fks::BDesc> host;   // outcome, copied back after the build
     uint64_t device_bytes;
     uint32_t schedule;
+    fks_allocator alloc;    // where the pools came from (has_alloc == 0: the default pool)
+    int has_alloc;
 };
 
 namespace fks {
@@ -659,8 +661,8 @@ using namespace fks;
 
 extern "C" int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_vals, const uint64_t* h_map_offsets,
                                    uint32_t M, uint64_t batch_seed, const fks_params* params, uint32_t schedule,
-                                   void* stream, fks_batch** out) {
-    if (!out || !h_map_offsets || M == 0) return FKS_EINVAL;
+                                   const fks_allocator* alloc, void* stream, fks_batch** out) {
+    if (!out || !h_map_offsets || M == 0 || !allocator_ok(alloc)) return FKS_EINVAL;
     fks_params P;
     fks_params_default(&P);
     if (params) P = *params;
@@ -669,8 +671,10 @@ extern "C" int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_val
     uint64_t total = h_map_offsets[M];
     if (total && (!d_keys || !d_vals)) return FKS_EINVAL;
     if (total * P.c >= (1ull << 40)) return FKS_EINVAL;
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
     fks_batch* B = new fks_batch;
+    keep_allocator(alloc, B->alloc, B->has_alloc);
     B->M = M;
     B->c = P.c;
     B->T = P.T;
@@ -838,6 +842,14 @@ extern "C" int fks_build_batch_u64(const uint64_t* d_keys, const uint32_t* d_val
             }
         }
     }
+    // a map whose every attempt was rejected: equal keys make it a broken precondition
+    for (uint32_t m = 0; rc == FKS_OK && m < M; ++m) {
+        BDesc& d = B->host[m];
+        if (d.status != FKS_EBUILD) continue;
+        bool equal = false;
+        rc = has_equal_keys(d_keys + d.key_off, d.n, nullptr, nullptr, st, &equal);
+        if (rc == FKS_OK && equal) d.status = FKS_EDUPKEY;
+    }
     cleanup_scratch();
     if (rc) {
         batch_release(B, st);
@@ -899,7 +911,13 @@ extern "C" int fks_batch_info(const fks_batch* B, uint32_t map_index, fks_map_in
     info->R = B->R;
     info->max_t = d.max_t;
     info->device_bytes = B->device_bytes;
-    return d.status == FKS_OK ? FKS_OK : d.status;
+    if (d.status != FKS_OK) return d.status;
+    int prev = 0;
+    FKS_HIP(hipGetDevice(&prev));
+    FKS_HIP(hipSetDevice(B->device));
+    const int rc = size_histogram(B->hdr_pool + d.hdr_off, d.n, info->size_hist);
+    (void)hipSetDevice(prev);
+    return rc;
 }
 
 extern "C" int fks_batch_export(const fks_batch* B, uint32_t map_index, void* h_header, void* h_slots,
@@ -951,6 +969,9 @@ extern "C" void fks_batch_destroy(fks_batch* B) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(B->device);
-    batch_release(B, nullptr);
+    {
+        AllocScope scope(B->has_alloc ? &B->alloc : nullptr);
+        batch_release(B, nullptr);
+    }
     (void)hipSetDevice(prev);
 }

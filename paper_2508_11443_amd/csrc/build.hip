@@ -377,7 +377,14 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     }
     drop_slots();
     release();
-    return rc ? rc : FKS_EBUILD;
+    if (rc) return rc;
+    // every attempt was rejected: equal keys, which no attempt can separate, make it a
+    // broken precondition rather than bad luck
+    bool equal = false;
+    if ((rc = has_equal_keys(bytes ? y : d_keys_in, n, bytes ? M->ctx_off : nullptr, bytes ? M->ctx_bytes : nullptr,
+                             st, &equal)))
+        return rc;
+    return equal ? FKS_EDUPKEY : FKS_EBUILD;
 }
 
 // keys: device u64 keys (or fingerprints); vals; aux_is_index for string maps
@@ -431,9 +438,10 @@ static void release_partial(fks_map* M, hipStream_t st) {
     delete M;
 }
 
-static fks_map* new_map(uint32_t kind, uint64_t n, uint64_t seed, const fks_params& P) {
+static fks_map* new_map(uint32_t kind, uint64_t n, uint64_t seed, const fks_params& P, const fks_allocator* alloc) {
     fks_map* M = new fks_map;
     std::memset(M, 0, sizeof(*M));
+    keep_allocator(alloc, M->alloc, M->has_alloc);
     M->kind = kind;
     M->n = n;
     M->seed = seed;
@@ -461,14 +469,15 @@ static int build_empty(fks_map* M, const fks_params& P, hipStream_t st) {
 }  // namespace fks
 
 extern "C" int fks_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint64_t seed,
-                             const fks_params* params, void* stream, fks_map** out) {
+                             const fks_params* params, const fks_allocator* alloc, void* stream, fks_map** out) {
     using namespace fks;
-    if (!out || (n && (!d_keys || !d_vals))) return FKS_EINVAL;
+    if (!out || (n && (!d_keys || !d_vals)) || !allocator_ok(alloc)) return FKS_EINVAL;
     fks_params P;
     int rc = check_params(n, params, P);
     if (rc) return rc;
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
-    fks_map* M = new_map(0, n, seed, P);
+    fks_map* M = new_map(0, n, seed, P, alloc);
     rc = n ? build_common(M, d_keys, d_vals, nullptr, nullptr, nullptr, 0, P, st) : build_empty(M, P, st);
     if (rc) {
         release_partial(M, st);
@@ -479,14 +488,16 @@ extern "C" int fks_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uin
 }
 
 extern "C" int fks_build_u64_v64(const uint64_t* d_keys, const uint64_t* d_vals, uint64_t n, uint64_t seed,
-                                 const fks_params* params, void* stream, fks_map** out) {
+                                 const fks_params* params, const fks_allocator* alloc, void* stream,
+                                 fks_map** out) {
     using namespace fks;
-    if (!out || (n && (!d_keys || !d_vals))) return FKS_EINVAL;
+    if (!out || (n && (!d_keys || !d_vals)) || !allocator_ok(alloc)) return FKS_EINVAL;
     fks_params P;
     int rc = check_params(n, params, P);
     if (rc) return rc;
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
-    fks_map* M = new_map(2, n, seed, P);
+    fks_map* M = new_map(2, n, seed, P, alloc);
     if (n == 0) {
         rc = build_empty(M, P, st);
     } else {
@@ -512,14 +523,15 @@ extern "C" int fks_build_u64_v64(const uint64_t* d_keys, const uint64_t* d_vals,
 
 extern "C" int fks_build_bytes(const int64_t* d_offsets, const uint8_t* d_bytes, uint64_t nbytes,
                                const uint32_t* d_vals, uint64_t n, uint64_t seed, const fks_params* params,
-                               void* stream, fks_map** out) {
+                               const fks_allocator* alloc, void* stream, fks_map** out) {
     using namespace fks;
-    if (!out || !d_offsets || (n && !d_vals) || (nbytes && !d_bytes)) return FKS_EINVAL;
+    if (!out || !d_offsets || (n && !d_vals) || (nbytes && !d_bytes) || !allocator_ok(alloc)) return FKS_EINVAL;
     fks_params P;
     int rc = check_params(n, params, P);
     if (rc) return rc;
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
-    fks_map* M = new_map(1, n, seed, P);
+    fks_map* M = new_map(1, n, seed, P, alloc);
     if (n) {
         rc = build_common(M, nullptr, d_vals, nullptr, d_offsets, d_bytes, nbytes, P, st);
     } else {

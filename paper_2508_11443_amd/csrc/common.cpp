@@ -32,8 +32,18 @@ static void configure_pool(int dev) {
     }
 }
 
+static thread_local const fks_allocator* tl_alloc = nullptr;
+
+AllocScope::AllocScope(const fks_allocator* a) : prev_(tl_alloc) { tl_alloc = a; }
+AllocScope::~AllocScope() { tl_alloc = prev_; }
+
 void* dev_alloc(size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 16;
+    if (tl_alloc) {
+        void* p = tl_alloc->alloc((uint64_t)bytes, (void*)s, tl_alloc->user);
+        if (!p) set_hip_error(hipErrorOutOfMemory);
+        return p;
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], configure_pool, dev);
@@ -47,8 +57,45 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     return p;
 }
 
+// per-workgroup LDS histogram of the 4-bit bucket sizes, folded into 16 global counters
+__global__ __launch_bounds__(256) void k_size_hist(const Group* __restrict__ header, uint64_t n,
+                                                     unsigned long long* __restrict__ hist) {
+    __shared__ uint32_t h[16];
+    if (threadIdx.x < 16) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t G = (n + 7) / 8;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = header[g].sizes;
+        const uint32_t k_end = g + 1 < G || n % 8 == 0 ? 8u : (uint32_t)(n % 8);
+        for (uint32_t k = 0; k < k_end; ++k) atomicAdd(&h[nib(w, k)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+int size_histogram(const Group* header, uint64_t n, uint64_t hist[16]) {
+    for (int s = 0; s < 16; ++s) hist[s] = 0;
+    if (n == 0) return FKS_OK;
+    unsigned long long* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, 16 * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(e);
+    uint64_t grid = ((n + 7) / 8 + 255) / 256;
+    if (grid > 1024) grid = 1024;
+    e = hipMemset(d, 0, 16 * sizeof(unsigned long long));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_size_hist, (unsigned)grid, 256, 0, nullptr, header, n, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(hist, d, 16 * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
 void dev_free(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    if (tl_alloc) tl_alloc->free(p, (void*)s, tl_alloc->user);
+    else (void)hipFreeAsync(p, s);
 }
 
 }  // namespace fks
@@ -95,7 +142,12 @@ int fks_info(const fks_map* map, fks_map_info* info) {
     info->R = map->R;
     info->max_t = map->max_t;
     info->device_bytes = map->device_bytes;
-    return FKS_OK;
+    int prev = 0;
+    FKS_HIP(hipGetDevice(&prev));
+    FKS_HIP(hipSetDevice(map->device));
+    const int rc = fks::size_histogram(map->header, map->n, info->size_hist);
+    (void)hipSetDevice(prev);
+    return rc;
 }
 
 int fks_export(const fks_map* map, void* h_header, void* h_slots, uint64_t* h_consts) {
@@ -118,12 +170,16 @@ void fks_destroy(fks_map* map) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(map->device);
-    // frees are ordered on the null stream, after all work already queued on it
-    fks::dev_free(map->header, nullptr);
-    fks::dev_free(map->slots, nullptr);
-    fks::dev_free(map->C, nullptr);
-    fks::dev_free(map->ctx_off, nullptr);
-    fks::dev_free(map->ctx_bytes, nullptr);
+    {
+        // the memory goes back where the build took it from; frees are ordered on the
+        // null stream, after all work already queued on it
+        fks::AllocScope scope(map->has_alloc ? &map->alloc : nullptr);
+        fks::dev_free(map->header, nullptr);
+        fks::dev_free(map->slots, nullptr);
+        fks::dev_free(map->C, nullptr);
+        fks::dev_free(map->ctx_off, nullptr);
+        fks::dev_free(map->ctx_bytes, nullptr);
+    }
     (void)hipSetDevice(prev);
     delete map;
 }

@@ -73,9 +73,11 @@ __global__ void k_dd_sentinel(const uint32_t* __restrict__ vals, uint64_t* __res
 using namespace fks;
 
 extern "C" int fks_build_u64_from_array(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t u, uint64_t seed,
-                                        const fks_params* params, void* stream, fks_map** out) {
-    if (!out || (u && (!d_keys || !d_vals)) || u >= (1ull << 30)) return FKS_EINVAL;
-    if (u == 0) return fks_build_u64(d_keys, d_vals, 0, seed, params, stream, out);
+                                        const fks_params* params, const fks_allocator* alloc, void* stream,
+                                        fks_map** out) {
+    if (!out || (u && (!d_keys || !d_vals)) || u >= (1ull << 30) || !allocator_ok(alloc)) return FKS_EINVAL;
+    if (u == 0) return fks_build_u64(d_keys, d_vals, 0, seed, params, alloc, stream, out);
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
     uint64_t cap = 1;
     while (cap < 2 * u) cap <<= 1;
@@ -117,7 +119,7 @@ extern "C" int fks_build_u64_from_array(const uint64_t* d_keys, const uint32_t* 
     dev_free(tidx, st);
     tkey = nullptr;
     tidx = nullptr;
-    int rc = fks_build_u64(dk, dv, n, seed, params, stream, out);
+    int rc = fks_build_u64(dk, dv, n, seed, params, alloc, stream, out);
     cleanup();
     return rc;
 }

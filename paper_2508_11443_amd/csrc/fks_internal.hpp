@@ -224,6 +224,8 @@ struct fks_map {
     uint8_t* ctx_bytes;   // bytes maps: copy of the context
     uint64_t ctx_nbytes;
     uint64_t device_bytes;
+    fks_allocator alloc;  // where the map's memory came from (has_alloc == 0: the default pool)
+    int has_alloc;
 };
 
 namespace fks {
@@ -232,10 +234,41 @@ namespace fks {
 void set_hip_error(hipError_t e);
 int hip_fail(hipError_t e);
 
-// device memory: stream-ordered allocations from the device's default pool,
-// which keeps freed blocks cached for the next build
+// Device memory.  dev_alloc / dev_free go to the allocator of the innermost
+// AllocScope on the calling thread: a caller's fks_allocator, or (none, or NULL)
+// stream-ordered allocations from the device's default pool, which keeps freed
+// blocks cached for the next build.  Every entry point that allocates opens a
+// scope with the caller's allocator (or, to release an object, the allocator
+// the object was built with), so all of a call's memory comes from one place.
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+class AllocScope {
+  public:
+    explicit AllocScope(const fks_allocator* a);
+    ~AllocScope();
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+
+  private:
+    const fks_allocator* prev_;
+};
+// a caller's allocator is usable: NULL, or both functions set
+inline bool allocator_ok(const fks_allocator* a) { return !a || (a->alloc && a->free); }
+// keep a copy of the caller's allocator in a built object
+inline void keep_allocator(const fks_allocator* a, fks_allocator& dst, int& has) {
+    has = a ? 1 : 0;
+    dst = a ? *a : fks_allocator{nullptr, nullptr, nullptr};
+}
+
+// hist[s] = buckets of size s among the first n buckets of the G group records at
+// `header` (the sizes of make_1); synchronous on the null stream
+int size_histogram(const Group* header, uint64_t n, uint64_t hist[16]);
+
+// *equal = whether keys[0..n) hold two equal entries; for string keys, `keys` are the
+// strings' fingerprints under one base and off/bytes the strings (else both nullptr).
+// Asked only when every level-one attempt of a build was rejected.  Synchronises `st`.
+int has_equal_keys(const uint64_t* keys, uint64_t n, const int64_t* off, const uint8_t* bytes, hipStream_t st,
+                   bool* equal);
 
 // pinned host staging for the small readbacks of a build
 struct Readback {

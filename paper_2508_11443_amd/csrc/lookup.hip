@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
     const Group* __restrict__ header, const Cell* __restrict__ slots, Triple A, uint64_t beta,
     uint64_t magic, uint32_t n, const Triple* __restrict__ Cg, uint32_t T,
     const int64_t* __restrict__ koff, const uint8_t* __restrict__ kbytes,
-    const int64_t* __restrict__ qoff, const uint8_t* __restrict__ qbytes, uint64_t m,
+    const int64_t* __restrict__ qoff, const uint8_t* __restrict__ qbytes, uint64_t qn, uint64_t m,
     uint32_t* __restrict__ vals, uint8_t* __restrict__ found, uint32_t missing) {
     __shared__ Triple C[kTMax];
     for (uint32_t t = threadIdx.x; t < T; t += kLBlock) C[t] = Cg[t];
@@ -103,6 +103,12 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
     for (uint64_t i = (uint64_t)blockIdx.x * kLBlock + threadIdx.x; i < m;
          i += (uint64_t)gridDim.x * kLBlock) {
         const int64_t a = qoff[i], b = qoff[i + 1];
+        if (a < 0 || b < a || (uint64_t)b > qn) {
+            // not a range of the needle buffer: nothing is read through it
+            if (WANT_VALS) vals[i] = missing;
+            if (found) found[i] = 0;
+            continue;
+        }
         const uint64_t len = (uint64_t)(b - a);
         const uint8_t* s = qbytes + a;
         uint32_t w[kChunkWords];
@@ -214,9 +220,10 @@ extern "C" int fks_lookup_u64_v64(const fks_map* map, const uint64_t* d_queries,
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
 
-static int lookup_bytes_impl(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes, uint64_t m,
-                             uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing, void* stream) {
-    if (!map || map->kind != 1 || (m && (!d_q_offsets || !d_q_bytes))) return FKS_EINVAL;
+static int lookup_bytes_impl(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
+                             uint64_t q_nbytes, uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out,
+                             uint32_t missing, void* stream) {
+    if (!map || map->kind != 1 || (m && !d_q_offsets) || (q_nbytes && !d_q_bytes)) return FKS_EINVAL;
     if (m == 0 || (!d_vals_out && !d_found_out)) return FKS_OK;
     hipStream_t st = (hipStream_t)stream;
     if (map->n == 0) {
@@ -227,23 +234,25 @@ static int lookup_bytes_impl(const fks_map* map, const int64_t* d_q_offsets, con
         if (d_vals_out)
             FKS_TIMED("fks_lookup_bytes", st, hipLaunchKernelGGL(k_lookup_bytes<true>, grid, kLBlock, 0, st, map->header, map->slots, map->A,
                                map->beta, map->magic_n, (uint32_t)map->n, map->C, map->T, map->ctx_off,
-                               map->ctx_bytes, d_q_offsets, d_q_bytes, m, d_vals_out, d_found_out, missing));
+                               map->ctx_bytes, d_q_offsets, d_q_bytes, q_nbytes, m, d_vals_out, d_found_out,
+                               missing));
         else
             FKS_TIMED("fks_contains_bytes", st, hipLaunchKernelGGL(k_lookup_bytes<false>, grid, kLBlock, 0, st, map->header, map->slots, map->A,
                                map->beta, map->magic_n, (uint32_t)map->n, map->C, map->T, map->ctx_off,
-                               map->ctx_bytes, d_q_offsets, d_q_bytes, m, d_vals_out, d_found_out, missing));
+                               map->ctx_bytes, d_q_offsets, d_q_bytes, q_nbytes, m, d_vals_out, d_found_out,
+                               missing));
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
 
 extern "C" int fks_lookup_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
-                                uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
-                                void* stream) {
-    return lookup_bytes_impl(map, d_q_offsets, d_q_bytes, m, d_vals_out, d_found_out, missing, stream);
+                                uint64_t q_nbytes, uint64_t m, uint32_t* d_vals_out, uint8_t* d_found_out,
+                                uint32_t missing, void* stream) {
+    return lookup_bytes_impl(map, d_q_offsets, d_q_bytes, q_nbytes, m, d_vals_out, d_found_out, missing, stream);
 }
 
 extern "C" int fks_contains_bytes(const fks_map* map, const int64_t* d_q_offsets, const uint8_t* d_q_bytes,
-                                  uint64_t m, uint8_t* d_found_out, void* stream) {
-    return lookup_bytes_impl(map, d_q_offsets, d_q_bytes, m, nullptr, d_found_out, 0, stream);
+                                  uint64_t q_nbytes, uint64_t m, uint8_t* d_found_out, void* stream) {
+    return lookup_bytes_impl(map, d_q_offsets, d_q_bytes, q_nbytes, m, nullptr, d_found_out, 0, stream);
 }

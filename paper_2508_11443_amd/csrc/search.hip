@@ -28,6 +28,8 @@ struct fks_sorted {
     int device;
     uint64_t* keys;   // n keys in layout order
     uint32_t* vals;   // their values
+    fks_allocator alloc;   // where keys and vals came from (has_alloc == 0: the default pool)
+    int has_alloc;
 };
 
 namespace fks {
@@ -298,10 +300,13 @@ static unsigned sgrid(uint64_t items, uint64_t per_block, unsigned cap) {
 using namespace fks;
 
 extern "C" int fks_sorted_build_u64(const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n, uint32_t layout,
-                                    void* stream, fks_sorted** out) {
-    if (!out || (n && (!d_keys || !d_vals)) || n >= (1ull << 32) || layout > 1) return FKS_EINVAL;
+                                    const fks_allocator* alloc, void* stream, fks_sorted** out) {
+    if (!out || (n && (!d_keys || !d_vals)) || n >= (1ull << 32) || layout > 1 || !allocator_ok(alloc))
+        return FKS_EINVAL;
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
     fks_sorted* S = new fks_sorted{};
+    keep_allocator(alloc, S->alloc, S->has_alloc);
     S->n = n;
     S->layout = layout;
     (void)hipGetDevice(&S->device);
@@ -445,9 +450,13 @@ extern "C" void fks_sorted_destroy(fks_sorted* S) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(S->device);
-    // frees are ordered on the null stream, after all work already queued on it
-    dev_free(S->keys, nullptr);
-    dev_free(S->vals, nullptr);
+    {
+        // back where the build took them from; frees are ordered on the null stream,
+        // after all work already queued on it
+        AllocScope scope(S->has_alloc ? &S->alloc : nullptr);
+        dev_free(S->keys, nullptr);
+        dev_free(S->vals, nullptr);
+    }
     (void)hipSetDevice(prev);
     delete S;
 }

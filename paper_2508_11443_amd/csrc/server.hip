@@ -152,6 +152,7 @@ struct fks_server {
         uint32_t* out_vals;
         uint8_t* out_found;
         uint32_t missing;
+        hipEvent_t ready = nullptr;   // recorded on the submitter's stream: the inputs are written
         double t_submit = 0, t_start = 0, t_done = 0;
         int status = 0;
         bool done = false;
@@ -180,8 +181,16 @@ static uint64_t estimate_bytes(uint64_t n, const fks_params& p) {
     return 16 * ((n + 7) / 8) + 16 * (uint64_t)p.c * n + sizeof(Triple) * p.T + 4096;
 }
 
-// evict least recently used idle maps until `need` more bytes fit; mu held
+// Evict least recently used idle maps until `need` more bytes fit; mu held.  Nothing is
+// evicted unless the idle maps free enough: false then, and the caller waits for pinned
+// maps to drain (or gives up when even that cannot make room).
 static bool make_room(fks_server* S, uint64_t need) {
+    if (S->used + need <= S->budget) return true;
+    if (need > S->budget) return false;
+    uint64_t idle = 0;
+    for (const auto& ms : S->maps)
+        if (ms.state == 2 && ms.pins == 0) idle += ms.bytes;
+    if (S->used - idle + need > S->budget) return false;
     while (S->used + need > S->budget) {
         int best = -1;
         for (size_t i = 0; i < S->maps.size(); ++i) {
@@ -202,6 +211,11 @@ static bool make_room(fks_server* S, uint64_t need) {
 
 static void finish_req(fks_server* S, uint64_t id, int status, double t) {
     auto& r = S->reqs[id];
+    if (r.ready) {
+        // every wait on it has been satisfied: the request's work is finished or never ran
+        (void)hipEventDestroy(r.ready);
+        r.ready = nullptr;
+    }
     r.status = status;
     r.t_done = t;
     r.done = true;
@@ -218,11 +232,14 @@ static void build_loop(fks_server* S) {
         const uint64_t id = S->build_q.front();
         auto& rq = S->reqs[id];
         const uint64_t est = estimate_bytes(rq.n, S->params);
-        // admission: wait until the reservation fits, evicting idle maps
-        while (!make_room(S, est)) {
-            bool any_pinned = false;
-            for (auto& ms : S->maps) any_pinned |= (ms.state == 2 && ms.pins > 0);
-            if (!any_pinned || S->stop) break;
+        // admission: wait until the reservation fits, evicting idle maps; a build larger
+        // than the whole budget fails at once and leaves the resident maps alone
+        while (est <= S->budget && !make_room(S, est)) {
+            // room can still appear once the lookups pinning resident maps drain
+            uint64_t ready_bytes = 0;
+            for (auto& ms : S->maps)
+                if (ms.state == 2) ready_bytes += ms.bytes;
+            if (S->used - ready_bytes + est > S->budget || S->stop) break;
             S->cv_build.wait_for(lk, std::chrono::milliseconds(1));
         }
         if (S->stop) return;
@@ -242,10 +259,13 @@ static void build_loop(fks_server* S) {
         const uint64_t* keys = rq.keys;
         const uint32_t* vals = rq.vals;
         const uint64_t n = rq.n, seed = rq.seed;
+        const hipEvent_t ready = rq.ready;
         fks_params p = S->params;
         lk.unlock();
         fks_map* m = nullptr;
-        int rc = fks_build_u64(keys, vals, n, seed, &p, S->build_st, &m);
+        // the build reads the keys only after the submitter's stream has written them
+        int rc = ready ? (hipStreamWaitEvent(S->build_st, ready, 0) == hipSuccess ? FKS_OK : FKS_EHIP) : FKS_OK;
+        if (rc == FKS_OK) rc = fks_build_u64(keys, vals, n, seed, &p, nullptr, S->build_st, &m);
         const double t = now_ms();
         lk.lock();
         S->used -= est;
@@ -289,30 +309,33 @@ static void lookup_loop(fks_server* S) {
     (void)hipSetDevice(S->device);
     struct Flight {
         bool busy = false;
+        int status = FKS_OK;   // FKS_EHIP when the launch could not be queued
         std::vector<uint64_t> ids;
     } flight[kRing];
     int next = 0;
     std::unique_lock<std::mutex> lk(S->mu);
+    // a launch whose event has completed: its requests are done; mu held
+    auto retire = [&](Flight& f) {
+        const double t = now_ms();
+        for (uint64_t id : f.ids) {
+            auto& r = S->reqs[id];
+            S->maps[r.map_id].pins--;
+            if (f.status == FKS_OK) S->queries_done += r.m;
+            finish_req(S, id, f.status, t);
+        }
+        f.busy = false;
+        f.status = FKS_OK;
+        f.ids.clear();
+        S->cv_done.notify_all();
+        S->cv_build.notify_all();
+    };
     for (;;) {
         // retire finished launches
         bool any_busy = false;
         for (int k = 0; k < kRing; ++k) {
             if (!flight[k].busy) continue;
-            if (hipEventQuery(S->ev[k]) == hipSuccess) {
-                const double t = now_ms();
-                for (uint64_t id : flight[k].ids) {
-                    auto& r = S->reqs[id];
-                    S->maps[r.map_id].pins--;
-                    S->queries_done += r.m;
-                    finish_req(S, id, FKS_OK, t);
-                }
-                flight[k].busy = false;
-                flight[k].ids.clear();
-                S->cv_done.notify_all();
-                S->cv_build.notify_all();
-            } else {
-                any_busy = true;
-            }
+            if (hipEventQuery(S->ev[k]) == hipSuccess) retire(flight[k]);
+            else any_busy = true;
         }
         // requests whose map is ready (or can never be)
         std::vector<uint64_t> ready;
@@ -351,23 +374,15 @@ static void lookup_loop(fks_server* S) {
             lk.unlock();
             (void)hipEventSynchronize(S->ev[next]);
             lk.lock();
-            const double t = now_ms();
-            for (uint64_t id : flight[next].ids) {
-                auto& r = S->reqs[id];
-                S->maps[r.map_id].pins--;
-                S->queries_done += r.m;
-                finish_req(S, id, FKS_OK, t);
-            }
-            flight[next].busy = false;
-            flight[next].ids.clear();
-            S->cv_done.notify_all();
-            S->cv_build.notify_all();
+            retire(flight[next]);
         }
         LTab* tab = S->h_tab[next];
         uint32_t tile0 = 0;
         uint32_t nr = 0;
+        std::vector<hipEvent_t> waits;
         for (uint64_t id : ready) {
             auto& r = S->reqs[id];
+            if (r.ready) waits.push_back(r.ready);
             auto& ms = S->maps[r.map_id];
             ms.last_use = ++S->clock;
             const fks_map* mp = ms.map;
@@ -401,16 +416,28 @@ static void lookup_loop(fks_server* S) {
         S->coalesced += nr;
         const size_t bytes = offsetof(LTab, reqs) + sizeof(LReq) * nr;
         lk.unlock();
-        hipError_t e = hipMemcpyAsync(S->d_tab[slot], tab, bytes, hipMemcpyHostToDevice, S->lookup_st);
-        hipGraphExec_t ex = S->use_graphs ? graph_for(S, slot, grid) : nullptr;
+        // the launch reads each request's needles only after its submitter's stream wrote them
+        hipError_t e = hipSuccess;
+        for (hipEvent_t w : waits)
+            if (e == hipSuccess) e = hipStreamWaitEvent(S->lookup_st, w, 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(S->d_tab[slot], tab, bytes, hipMemcpyHostToDevice, S->lookup_st);
         bool replayed = false;
-        if (e == hipSuccess && ex) replayed = hipGraphLaunch(ex, S->lookup_st) == hipSuccess;
-        if (!replayed) {
-            FKS_TIMED("fks_lookup_multi", S->lookup_st,
-                      hipLaunchKernelGGL(k_lookup_multi, grid, 256, 0, S->lookup_st, S->d_tab[slot]));
+        if (e == hipSuccess) {
+            hipGraphExec_t ex = S->use_graphs ? graph_for(S, slot, grid) : nullptr;
+            if (ex) replayed = hipGraphLaunch(ex, S->lookup_st) == hipSuccess;
+            if (!replayed) {
+                FKS_TIMED("fks_lookup_multi", S->lookup_st,
+                          hipLaunchKernelGGL(k_lookup_multi, grid, 256, 0, S->lookup_st, S->d_tab[slot]));
+                e = hipGetLastError();
+            }
         }
+        // the slot retires when this event completes (at once when nothing was queued)
         (void)hipEventRecord(S->ev[slot], S->lookup_st);
         lk.lock();
+        if (e != hipSuccess) {
+            set_hip_error(e);
+            flight[slot].status = FKS_EHIP;
+        }
         if (replayed) S->graph_replays++;
     }
 }
@@ -456,9 +483,25 @@ extern "C" int fks_server_create(uint64_t budget_bytes, const fks_params* params
     return FKS_OK;
 }
 
+// an event recorded on the submitter's stream now: the server's work on the request waits for it
+static int mark_ready(void* stream, hipEvent_t* ev) {
+    hipError_t e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        e = hipEventRecord(*ev, (hipStream_t)stream);
+        if (e != hipSuccess) (void)hipEventDestroy(*ev);
+    }
+    if (e != hipSuccess) {
+        *ev = nullptr;
+        return hip_fail(e);
+    }
+    return FKS_OK;
+}
+
 extern "C" int fks_server_submit_build(fks_server* S, const uint64_t* d_keys, const uint32_t* d_vals, uint64_t n,
-                                       uint64_t seed, uint64_t* req_id, uint32_t* map_id) {
+                                       uint64_t seed, void* stream, uint64_t* req_id, uint32_t* map_id) {
     if (!S || (n && (!d_keys || !d_vals)) || n >= (1ull << 30)) return FKS_EINVAL;
+    hipEvent_t ready = nullptr;
+    if (int rc = mark_ready(stream, &ready)) return rc;
     std::lock_guard<std::mutex> lk(S->mu);
     const uint64_t id = S->reqs.size();
     fks_server::Req r;
@@ -472,6 +515,7 @@ extern "C" int fks_server_submit_build(fks_server* S, const uint64_t* d_keys, co
     r.out_vals = nullptr;
     r.out_found = nullptr;
     r.missing = 0;
+    r.ready = ready;
     r.t_submit = now_ms();
     if (S->first_submit < 0) S->first_submit = r.t_submit;
     S->reqs.push_back(r);
@@ -485,10 +529,17 @@ extern "C" int fks_server_submit_build(fks_server* S, const uint64_t* d_keys, co
 
 extern "C" int fks_server_submit_lookup(fks_server* S, uint32_t map_id, const uint64_t* d_queries, uint64_t m,
                                         uint32_t* d_vals_out, uint8_t* d_found_out, uint32_t missing,
-                                        uint64_t* req_id) {
+                                        void* stream, uint64_t* req_id) {
     if (!S || (m && !d_queries)) return FKS_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (map_id >= S->maps.size()) return FKS_EINVAL;
+    }
+    hipEvent_t ready = nullptr;
+    if (m) {
+        if (int rc = mark_ready(stream, &ready)) return rc;
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    if (map_id >= S->maps.size()) return FKS_EINVAL;
     const uint64_t id = S->reqs.size();
     fks_server::Req r;
     r.kind = 1;
@@ -501,6 +552,7 @@ extern "C" int fks_server_submit_lookup(fks_server* S, uint32_t map_id, const ui
     r.out_vals = d_vals_out;
     r.out_found = d_found_out;
     r.missing = missing;
+    r.ready = ready;
     r.t_submit = now_ms();
     if (S->first_submit < 0) S->first_submit = r.t_submit;
     S->reqs.push_back(r);

@@ -21,6 +21,7 @@ namespace fks {
 constexpr int kVBlock = 256;
 constexpr uint32_t kVPartials = 65536;  // most workgroups of the reduction's first pass (one group per lane up to 2^27 keys)
 
+
 __device__ __forceinline__ uint64_t cell_value(const Cell& c, bool v64) {
     return v64 ? ((uint64_t)c.aux << 32) | c.val : (uint64_t)c.val;
 }
@@ -142,9 +143,10 @@ static void free_map(fks_map* M, hipStream_t st) {
 using namespace fks;
 
 extern "C" int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint64_t b, const void* d_table,
-                              uint64_t table_len, void* stream, fks_map** out) {
-    if (!map || !out || op > FKS_VOP_GATHER) return FKS_EINVAL;
+                              uint64_t table_len, const fks_allocator* alloc, void* stream, fks_map** out) {
+    if (!map || !out || op > FKS_VOP_GATHER || !allocator_ok(alloc)) return FKS_EINVAL;
     if (op == FKS_VOP_GATHER && table_len && !d_table) return FKS_EINVAL;
+    AllocScope scope(alloc);
     hipStream_t st = (hipStream_t)stream;
     const bool v64 = map->kind == 2;
     const uint64_t G = (map->n + 7) / 8;
@@ -152,6 +154,7 @@ extern "C" int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint6
     // the new map: the same keys, attempt and parameters; its own copies of the header, the
     // triples and a string map's context, and cells with the mapped values
     fks_map* M = new fks_map(*map);
+    keep_allocator(alloc, M->alloc, M->has_alloc);   // the new map's memory comes from this call's allocator
     M->header = nullptr;
     M->slots = nullptr;
     M->C = nullptr;
@@ -203,31 +206,50 @@ extern "C" int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint6
     return FKS_OK;
 }
 
-extern "C" int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream) {
-    if (!map || !d_out || op > FKS_VRED_XOR) return FKS_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
+namespace fks {
+
+// workgroups of the reduction's first pass (each strides over the table beyond that)
+static uint32_t reduce_partials(const fks_map* map) {
+    const uint64_t G = (map->n + 7) / 8;
+    uint64_t np = (G + kVBlock - 1) / kVBlock;
+    return (uint32_t)(np > kVPartials ? kVPartials : np);
+}
+
+// the two passes of the reduction into `partial` (room for reduce_partials(map) entries)
+static int reduce_launch(const fks_map* map, uint32_t op, uint64_t* d_out, uint64_t* partial, hipStream_t st) {
     const bool v64 = map->kind == 2;
     // the identity of the operation in the map's value width
     const uint64_t ident = op == FKS_VRED_MIN ? (v64 ? ~0ull : 0xFFFFFFFFull) : 0ull;
     const uint64_t G = (map->n + 7) / 8;
+    const uint32_t np = reduce_partials(map);
     if (G == 0) {
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, nullptr, 0u, op, ident, d_out);
     } else {
-        uint64_t np = (G + kVBlock - 1) / kVBlock;
-        if (np > kVPartials) np = kVPartials;
-        uint64_t* partial = (uint64_t*)dev_alloc(8 * np, st);
-        if (!partial) return FKS_ENOMEM;
         if (v64)
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_groups<true>, (unsigned)np, kVBlock, 0, st, map->header, map->slots,
-                                         G, map->S, map->C, map->T, op, ident, partial));
+                      hipLaunchKernelGGL(k_reduce_groups<true>, np, kVBlock, 0, st, map->header, map->slots, G,
+                                         map->S, map->C, map->T, op, ident, partial));
         else
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_groups<false>, (unsigned)np, kVBlock, 0, st, map->header,
-                                         map->slots, G, map->S, map->C, map->T, op, ident, partial));
-        hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, partial, (uint32_t)np, op, ident, d_out);
-        dev_free(partial, st);
+                      hipLaunchKernelGGL(k_reduce_groups<false>, np, kVBlock, 0, st, map->header, map->slots, G,
+                                         map->S, map->C, map->T, op, ident, partial));
+        hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, partial, np, op, ident, d_out);
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? FKS_OK : hip_fail(e);
+}
+
+}  // namespace fks
+
+extern "C" int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream) {
+    if (!map || !d_out || op > FKS_VRED_XOR) return FKS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t* partial = nullptr;
+    if (map->n) {
+        partial = (uint64_t*)dev_alloc(8ull * reduce_partials(map), st);
+        if (!partial) return FKS_ENOMEM;
+    }
+    const int rc = reduce_launch(map, op, d_out, partial, st);
+    dev_free(partial, st);
+    return rc;
 }

@@ -44,7 +44,62 @@ class fks_map_info(ctypes.Structure):
                 ("slot_bytes", ctypes.c_uint64), ("ctx_bytes", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("r", ctypes.c_uint32), ("kind", ctypes.c_uint32),
                 ("c", ctypes.c_uint32), ("T", ctypes.c_uint32), ("R", ctypes.c_uint32),
-                ("max_t", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+                ("max_t", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
+                ("size_hist", ctypes.c_uint64 * 16)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class fks_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class Allocator:
+    """An fks_allocator backed by two Python callables: alloc(nbytes, stream) -> device address
+    or 0, free(address, stream).  The object must outlive every map built with it (the map
+    returns its memory through it in fks_destroy); the binding's map objects keep a reference."""
+
+    def __init__(self, alloc, free):
+        def _alloc(nbytes, stream, user):
+            try:
+                return alloc(int(nbytes), stream or 0) or None
+            except Exception:
+                return None
+
+        def _free(ptr, stream, user):
+            free(int(ptr), stream or 0)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.struct = fks_allocator(self._alloc_cb, self._free_cb, None)
+
+    def pointer(self):
+        return ctypes.byref(self.struct)
+
+
+def torch_allocator(device=None) -> Allocator:
+    """Device memory from torch's caching allocator (torch.cuda.caching_allocator_alloc on
+    the stream the library names, caching_allocator_delete to release), so that a map's
+    memory is visible to, and reused by, the allocator the rest of the program uses.  Each
+    allocation is a call from C back into Python (a few microseconds), so builds that
+    allocate little and often may prefer the default (allocator=None: the device's
+    stream-ordered pool)."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, dev, stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return Allocator(alloc, free)
+
+
+def _alloc_arg(allocator):
+    return None if allocator is None else allocator.pointer()
 
 
 _lib = None
@@ -53,24 +108,24 @@ _lib = None
 _VP, _U64, _U32, _I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
 SIGNATURES = [
     ("fks_params_default", None, [_VP]),
-    ("fks_build_u64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
-    ("fks_build_u64_from_array", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
-    ("fks_build_u64_v64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_u64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_u64_from_array", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_u64_v64", _I32, [_VP, _VP, _U64, _U64, _VP, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_lookup_u64_v64", _I32, [_VP, _VP, _U64, _VP, _VP, _U64, _VP]),
-    ("fks_build_bytes", _I32, [_VP, _VP, _U64, _VP, _U64, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_bytes", _I32, [_VP, _VP, _U64, _VP, _U64, _U64, _VP, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_lookup_u64", _I32, [_VP, _VP, _U64, _VP, _VP, _U32, _VP]),
     ("fks_contains_u64", _I32, [_VP, _VP, _U64, _VP, _VP]),
-    ("fks_lookup_bytes", _I32, [_VP, _VP, _VP, _U64, _VP, _VP, _U32, _VP]),
-    ("fks_contains_bytes", _I32, [_VP, _VP, _VP, _U64, _VP, _VP]),
+    ("fks_lookup_bytes", _I32, [_VP, _VP, _VP, _U64, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_contains_bytes", _I32, [_VP, _VP, _VP, _U64, _U64, _VP, _VP]),
     ("fks_info", _I32, [_VP, _VP]),
-    ("fks_map_values", _I32, [_VP, _U32, _U64, _U64, _VP, _U64, _VP, ctypes.POINTER(_VP)]),
+    ("fks_map_values", _I32, [_VP, _U32, _U64, _U64, _VP, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_reduce_values", _I32, [_VP, _U32, _VP, _VP]),
     ("fks_export", _I32, [_VP, _VP, _VP, _VP]),
     ("fks_destroy", None, [_VP]),
     ("fks_strerror", ctypes.c_char_p, [_I32]),
     ("fks_last_hip_error", _I32, []),
     ("fks_version", _I32, []),
-    ("fks_build_batch_u64", _I32, [_VP, _VP, _VP, _U32, _U64, _VP, _U32, _VP, ctypes.POINTER(_VP)]),
+    ("fks_build_batch_u64", _I32, [_VP, _VP, _VP, _U32, _U64, _VP, _U32, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_lookup_batch_u64", _I32, [_VP, _VP, _VP, _U64, _VP, _VP, _U32, _VP]),
     ("fks_batch_status", _I32, [_VP, _VP, _VP, _VP]),
     ("fks_batch_info", _I32, [_VP, _U32, _VP]),
@@ -79,8 +134,8 @@ SIGNATURES = [
     ("fks_batch_set_schedule", _I32, [_U32, _U64, _U32]),
     ("fks_batch_schedules", _I32, [_VP, _I32]),
     ("fks_server_create", _I32, [_U64, _VP, _U32, ctypes.POINTER(_VP)]),
-    ("fks_server_submit_build", _I32, [_VP, _VP, _VP, _U64, _U64, _VP, _VP]),
-    ("fks_server_submit_lookup", _I32, [_VP, _U32, _VP, _U64, _VP, _VP, _U32, _VP]),
+    ("fks_server_submit_build", _I32, [_VP, _VP, _VP, _U64, _U64, _VP, _VP, _VP]),
+    ("fks_server_submit_lookup", _I32, [_VP, _U32, _VP, _U64, _VP, _VP, _U32, _VP, _VP]),
     ("fks_server_poll", _I32, [_VP, _U64, _VP, _VP, _VP]),
     ("fks_server_wait_all", _I32, [_VP]),
     ("fks_server_latencies", _I32, [_VP, _VP, _VP, _VP, _VP, _U64]),
@@ -88,7 +143,7 @@ SIGNATURES = [
     ("fks_server_map", _VP, [_VP, _U32]),
     ("fks_server_destroy", None, [_VP]),
     ("fks_probe_random_reads", _I32, [_U64, _U64, _U32, _VP, ctypes.POINTER(ctypes.c_double)]),
-    ("fks_sorted_build_u64", _I32, [_VP, _VP, _U64, _U32, _VP, ctypes.POINTER(_VP)]),
+    ("fks_sorted_build_u64", _I32, [_VP, _VP, _U64, _U32, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_sorted_lookup_u64", _I32, [_VP, _VP, _U64, _VP, _VP, _U32, _VP]),
     ("fks_sorted_export", _I32, [_VP, _VP, _VP]),
     ("fks_sorted_info", _I32, [_VP, _VP, _VP]),
@@ -177,12 +232,20 @@ def _params(c=None, T=None, R=None, schedule=None):
     return p
 
 
-class FksMap:
-    """A built map; owns the C handle and releases it with fks_destroy."""
+def _info_dict(inf) -> dict:
+    d = {name: getattr(inf, name) for name, _ in fks_map_info._fields_}
+    d["size_hist"] = [int(x) for x in inf.size_hist]
+    return d
 
-    def __init__(self, handle: int, kind: str):
+
+class FksMap:
+    """A built map; owns the C handle and releases it with fks_destroy (through the allocator
+    it was built with, which the object keeps alive)."""
+
+    def __init__(self, handle: int, kind: str, allocator=None):
         self._h = ctypes.c_void_p(handle)
         self.kind = kind
+        self._allocator = allocator
 
     @property
     def handle(self):
@@ -191,7 +254,7 @@ class FksMap:
     def info(self) -> dict:
         inf = fks_map_info()
         _check(_load().fks_info(self._h, ctypes.byref(inf)), "fks_info")
-        return {name: getattr(inf, name) for name, _ in fks_map_info._fields_}
+        return _info_dict(inf)
 
     def destroy(self):
         if self._h is not None and self._h.value:
@@ -205,21 +268,26 @@ class FksMap:
             pass
 
 
-def fks_build_u64(keys, vals, seed: int, c=None, T=None, R=None, stream=None, schedule=None) -> FksMap:
+def fks_build_u64(keys, vals, seed: int, c=None, T=None, R=None, stream=None, schedule=None,
+                  allocator=None) -> FksMap:
     """from_array_nodup over n uint64 keys (device tensor, int64 or uint64) and uint32 values.
-    schedule=1 searches level two with the paper's flattened rounds (same table)."""
+    schedule=1 searches level two with the paper's flattened rounds (same table).
+    allocator: an Allocator (e.g. torch_allocator()) for the map and the build's scratch, or
+    None for the device's stream-ordered pool."""
     n = keys.numel()
     if vals.numel() != n:
         raise ValueError("keys and values differ in length")
     p = _params(c, T, R, schedule)
     out = ctypes.c_void_p()
     rc = _load().fks_build_u64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
-                               seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
+                               seed & ((1 << 64) - 1), ctypes.byref(p), _alloc_arg(allocator), _stream(stream),
+                               ctypes.byref(out))
     _check(rc, "fks_build_u64")
-    return FksMap(out.value, "u64")
+    return FksMap(out.value, "u64", allocator)
 
 
-def fks_build_u64_from_array(keys, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+def fks_build_u64_from_array(keys, vals, seed: int, c=None, T=None, R=None, stream=None,
+                             allocator=None) -> FksMap:
     """from_array: keys may repeat; a repeated key keeps the value of its first occurrence."""
     n = keys.numel()
     if vals.numel() != n:
@@ -227,13 +295,13 @@ def fks_build_u64_from_array(keys, vals, seed: int, c=None, T=None, R=None, stre
     p = _params(c, T, R)
     out = ctypes.c_void_p()
     rc = _load().fks_build_u64_from_array(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
-                                          seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
-                                          ctypes.byref(out))
+                                          seed & ((1 << 64) - 1), ctypes.byref(p), _alloc_arg(allocator),
+                                          _stream(stream), ctypes.byref(out))
     _check(rc, "fks_build_u64_from_array")
-    return FksMap(out.value, "u64")
+    return FksMap(out.value, "u64", allocator)
 
 
-def fks_build_u64_v64(keys, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+def fks_build_u64_v64(keys, vals, seed: int, c=None, T=None, R=None, stream=None, allocator=None) -> FksMap:
     """from_array_nodup with 64-bit values (device tensor, int64 or uint64)."""
     n = keys.numel()
     if vals.numel() != n:
@@ -241,12 +309,14 @@ def fks_build_u64_v64(keys, vals, seed: int, c=None, T=None, R=None, stream=None
     p = _params(c, T, R)
     out = ctypes.c_void_p()
     rc = _load().fks_build_u64_v64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u64_types(), "vals"), n,
-                                   seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream), ctypes.byref(out))
+                                   seed & ((1 << 64) - 1), ctypes.byref(p), _alloc_arg(allocator),
+                                   _stream(stream), ctypes.byref(out))
     _check(rc, "fks_build_u64_v64")
-    return FksMap(out.value, "u64v64")
+    return FksMap(out.value, "u64v64", allocator)
 
 
-def fks_map_values(m: FksMap, op: int, a: int = 0, b: int = 0, table=None, stream=None) -> FksMap:
+def fks_map_values(m: FksMap, op: int, a: int = 0, b: int = 0, table=None, stream=None,
+                   allocator=None) -> FksMap:
     """A new map with the keys of m and op(v) as values (FKS_VOP_*); table: the device tensor
     FKS_VOP_GATHER reads (uint32 entries, or 64-bit for maps with 64-bit values)."""
     if table is not None:
@@ -256,10 +326,10 @@ def fks_map_values(m: FksMap, op: int, a: int = 0, b: int = 0, table=None, strea
         d_table, n_table = None, 0
     out = ctypes.c_void_p()
     mask = (1 << 64) - 1
-    rc = _load().fks_map_values(m.handle, op, a & mask, b & mask, d_table, n_table, _stream(stream),
-                                ctypes.byref(out))
+    rc = _load().fks_map_values(m.handle, op, a & mask, b & mask, d_table, n_table, _alloc_arg(allocator),
+                                _stream(stream), ctypes.byref(out))
     _check(rc, "fks_map_values")
-    return FksMap(out.value, m.kind)
+    return FksMap(out.value, m.kind, allocator)
 
 
 def fks_reduce_values(m: FksMap, op: int, out=None, stream=None):
@@ -289,7 +359,8 @@ def fks_lookup_u64_v64(m: FksMap, queries, vals_out, found_out=None, missing: in
     _check(rc, "fks_lookup_u64_v64")
 
 
-def fks_build_bytes(offsets, data, vals, seed: int, c=None, T=None, R=None, stream=None) -> FksMap:
+def fks_build_bytes(offsets, data, vals, seed: int, c=None, T=None, R=None, stream=None,
+                    allocator=None) -> FksMap:
     """from_array_nodup over n byte-string keys given as CSR (int64 offsets[n+1], uint8 bytes)."""
     import torch
     n = offsets.numel() - 1
@@ -300,10 +371,10 @@ def fks_build_bytes(offsets, data, vals, seed: int, c=None, T=None, R=None, stre
     rc = _load().fks_build_bytes(_dev(offsets, (torch.int64,), "offsets"),
                                  _dev(data, (torch.uint8,), "bytes") if data.numel() else None,
                                  data.numel(), _dev(vals, _u32_types(), "vals"), n,
-                                 seed & ((1 << 64) - 1), ctypes.byref(p), _stream(stream),
-                                 ctypes.byref(out))
+                                 seed & ((1 << 64) - 1), ctypes.byref(p), _alloc_arg(allocator),
+                                 _stream(stream), ctypes.byref(out))
     _check(rc, "fks_build_bytes")
-    return FksMap(out.value, "bytes")
+    return FksMap(out.value, "bytes", allocator)
 
 
 def fks_lookup_u64(m: FksMap, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):
@@ -329,8 +400,8 @@ def fks_lookup_bytes(m: FksMap, q_offsets, q_data, vals_out, found_out, missing:
     import torch
     _fits(q_offsets.numel() - 1, vals_out=vals_out, found_out=found_out)
     rc = _load().fks_lookup_bytes(m.handle, _dev(q_offsets, (torch.int64,), "q_offsets"),
-                                  _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else ctypes.c_void_p(q_offsets.data_ptr()),
-                                  q_offsets.numel() - 1, _dev(vals_out, _u32_types(), "vals_out"),
+                                  _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else None,
+                                  q_data.numel(), q_offsets.numel() - 1, _dev(vals_out, _u32_types(), "vals_out"),
                                   _dev(found_out, (torch.uint8, torch.bool), "found_out"),
                                   missing & 0xFFFFFFFF, _stream(stream))
     _check(rc, "fks_lookup_bytes")
@@ -340,8 +411,9 @@ def fks_contains_bytes(m: FksMap, q_offsets, q_data, found_out, stream=None):
     import torch
     _fits(q_offsets.numel() - 1, found_out=found_out)
     rc = _load().fks_contains_bytes(m.handle, _dev(q_offsets, (torch.int64,), "q_offsets"),
-                                    _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else ctypes.c_void_p(q_offsets.data_ptr()),
-                                    q_offsets.numel() - 1, _dev(found_out, (torch.uint8, torch.bool), "found_out"),
+                                    _dev(q_data, (torch.uint8,), "q_bytes") if q_data.numel() else None,
+                                    q_data.numel(), q_offsets.numel() - 1,
+                                    _dev(found_out, (torch.uint8, torch.bool), "found_out"),
                                     _stream(stream))
     _check(rc, "fks_contains_bytes")
 
@@ -393,9 +465,10 @@ def fks_prof_read() -> dict:
 class FksBatch:
     """M independent maps built in one persistent launch; owns the C handle."""
 
-    def __init__(self, handle: int, M: int):
+    def __init__(self, handle: int, M: int, allocator=None):
         self._h = ctypes.c_void_p(handle)
         self.M = M
+        self._allocator = allocator
 
     @property
     def handle(self):
@@ -423,7 +496,7 @@ class FksBatch:
 
 
 def fks_build_batch_u64(keys, vals, map_offsets, batch_seed: int, c=None, T=None, R=None, schedule: int = 0,
-                        stream=None) -> FksBatch:
+                        stream=None, allocator=None) -> FksBatch:
     """Build M maps: map m holds keys[map_offsets[m]:map_offsets[m+1]] (host offsets, M+1 entries)."""
     import numpy as np
     off = np.ascontiguousarray(map_offsets, np.uint64)
@@ -433,9 +506,9 @@ def fks_build_batch_u64(keys, vals, map_offsets, batch_seed: int, c=None, T=None
     rc = _load().fks_build_batch_u64(_dev(keys, _u64_types(), "keys") if keys.numel() else None,
                                      _dev(vals, _u32_types(), "vals") if vals.numel() else None,
                                      off.ctypes.data, M, batch_seed & ((1 << 64) - 1), ctypes.byref(p),
-                                     schedule, _stream(stream), ctypes.byref(out))
+                                     schedule, _alloc_arg(allocator), _stream(stream), ctypes.byref(out))
     _check(rc, "fks_build_batch_u64")
-    return FksBatch(out.value, M)
+    return FksBatch(out.value, M, allocator)
 
 
 def fks_lookup_batch_u64(b: FksBatch, map_ids, queries, vals_out, found_out, missing: int = 0xFFFFFFFF,
@@ -462,7 +535,7 @@ def fks_batch_export(b: FksBatch, index: int):
     rc = _load().fks_batch_export(b.handle, index, header.ctypes.data if header.size else None,
                                   slots.ctypes.data if slots.size else None, consts.ctypes.data)
     _check(rc, "fks_batch_export")
-    return header, slots, consts, {name: getattr(inf, name) for name, _ in fks_map_info._fields_}
+    return header, slots, consts, _info_dict(inf)
 
 
 def fks_batch_schedules():
@@ -505,23 +578,27 @@ class FksServer:
         self._h = out
         self._keep = {}
 
-    def submit_build(self, keys, vals, seed: int):
+    def submit_build(self, keys, vals, seed: int, stream=None):
+        """Queue a build; its device work is ordered after everything already queued on
+        `stream` (default: torch's current stream), so the keys may still be in flight."""
         rid, mid = ctypes.c_uint64(), ctypes.c_uint32()
         _check(_load().fks_server_submit_build(self._h, _dev(keys, _u64_types(), "keys"),
                                                _dev(vals, _u32_types(), "vals"), keys.numel(),
-                                               seed & ((1 << 64) - 1), ctypes.byref(rid), ctypes.byref(mid)),
+                                               seed & ((1 << 64) - 1), _stream(stream), ctypes.byref(rid),
+                                               ctypes.byref(mid)),
                "fks_server_submit_build")
         self._keep[rid.value] = (keys, vals)
         return rid.value, mid.value
 
-    def submit_lookup(self, map_id: int, queries, vals_out, found_out, missing: int = 0xFFFFFFFF):
+    def submit_lookup(self, map_id: int, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):
+        """Queue a lookup, ordered after `stream` as submit_build is."""
         import torch
         _fits(queries.numel(), vals_out=vals_out, found_out=found_out)
         rid = ctypes.c_uint64()
         _check(_load().fks_server_submit_lookup(self._h, map_id, _dev(queries, _u64_types(), "queries"),
                                                 queries.numel(), _dev(vals_out, _u32_types(), "vals_out"),
                                                 _dev(found_out, (torch.uint8, torch.bool), "found_out"),
-                                                missing & 0xFFFFFFFF, ctypes.byref(rid)),
+                                                missing & 0xFFFFFFFF, _stream(stream), ctypes.byref(rid)),
                "fks_server_submit_lookup")
         self._keep[rid.value] = (queries, vals_out, found_out)
         return rid.value
@@ -581,9 +658,10 @@ def fks_probe_random_reads(buffer_bytes: int = 2 << 30, probes: int = 1 << 27, w
 class FksSorted:
     """A sorted-array or Eytzinger-layout map; released with fks_sorted_destroy."""
 
-    def __init__(self, handle: int, layout: int):
+    def __init__(self, handle: int, layout: int, allocator=None):
         self._h = ctypes.c_void_p(handle)
         self.layout = layout
+        self._allocator = allocator
 
     @property
     def handle(self):
@@ -606,15 +684,15 @@ class FksSorted:
             pass
 
 
-def fks_sorted_build_u64(keys, vals, layout: int = FKS_LAYOUT_SORTED, stream=None) -> FksSorted:
+def fks_sorted_build_u64(keys, vals, layout: int = FKS_LAYOUT_SORTED, stream=None, allocator=None) -> FksSorted:
     n = keys.numel()
     if vals.numel() != n:
         raise ValueError("keys and values differ in length")
     out = ctypes.c_void_p()
     rc = _load().fks_sorted_build_u64(_dev(keys, _u64_types(), "keys"), _dev(vals, _u32_types(), "vals"), n,
-                                      layout, _stream(stream), ctypes.byref(out))
+                                      layout, _alloc_arg(allocator), _stream(stream), ctypes.byref(out))
     _check(rc, "fks_sorted_build_u64")
-    return FksSorted(out.value, layout)
+    return FksSorted(out.value, layout, allocator)
 
 
 def fks_sorted_lookup_u64(s: FksSorted, queries, vals_out, found_out, missing: int = 0xFFFFFFFF, stream=None):

@@ -72,9 +72,11 @@ def absent_u64(keys_sorted: np.ndarray, count: int, rng) -> np.ndarray:
     return out[:count]
 
 
-def u64_queries(keys: np.ndarray, m: int, hit_fraction: float, seed: int):
+def u64_queries(keys: np.ndarray, m: int, hit_fraction: float, seed: int, return_index: bool = False):
     """m queries: a hit_fraction of present keys (no repeats while possible) and uniform absent
-    keys, in uniform random order.  Returns (queries, expected_found uint8)."""
+    keys, in uniform random order.  Returns (queries, expected_found uint8), and with
+    return_index also the position in `keys` of each present query (-1 for absent ones); the
+    draws are the same either way."""
     rng = _rng(seed)
     nh = int(round(m * hit_fraction))
     if keys.size == 0:
@@ -91,7 +93,10 @@ def u64_queries(keys: np.ndarray, m: int, hit_fraction: float, seed: int):
     q = np.concatenate([hits, miss])
     found = np.concatenate([np.ones(nh, np.uint8), np.zeros(m - nh, np.uint8)])
     perm = rng.permutation(m)
-    return q[perm], found[perm]
+    if not return_index:
+        return q[perm], found[perm]
+    src = np.concatenate([idx.astype(np.int64) if nh else np.zeros(0, np.int64), np.full(m - nh, -1, np.int64)])
+    return q[perm], found[perm], src[perm]
 
 
 # ---- byte strings ----------------------------------------------------------

@@ -142,3 +142,82 @@ def test_open_loop_stream_latencies():
     res, outs = serve.run(wl, 16 << 30)
     assert res["status_ok"] and serve.check(wl, outs)
     assert 0 < res["lookup_p50_ms"] <= res["lookup_p99_ms"]
+
+
+def _busy(stream, dev):
+    """Queue some tens of milliseconds of device work on `stream` (a bounded chain of
+    elementwise kernels), so that whatever follows on it is still pending for a while."""
+    import torch
+    with torch.cuda.stream(stream):
+        x = torch.ones(1 << 25, dtype=torch.float32, device=dev)
+        for _ in range(400):
+            x = x * 1.0001 + 0.5
+    return x
+
+
+def test_requests_are_ordered_after_the_submitters_stream():
+    """Keys and needles written on a side stream behind pending work are submitted at once,
+    without any host synchronisation: the server's work waits for that stream, so the map
+    equals a standalone build and every needle is answered exactly."""
+    import torch
+    fks, serve = _mods()
+    dev = torch.device("cuda:0")
+    announce("gpu serve: requests ordered after the submitter's stream")
+    n = 200000
+    side = torch.cuda.Stream()
+    keys = torch.empty(n, dtype=torch.int64, device=dev)
+    vals = torch.empty(n, dtype=torch.int32, device=dev)
+    q = torch.empty(n, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    srv = fks.FksServer(8 << 30)
+    _busy(side, dev)
+    with torch.cuda.stream(side):
+        keys.copy_(workloads.mix_keys_torch(torch.arange(0, n, dtype=torch.int64, device=dev)))
+        vals.copy_(torch.arange(n, dtype=torch.int32, device=dev))
+        # needles: the keys in reverse order, then keys that are not in the map
+        q[: n // 2].copy_(keys[: n // 2].flip(0))
+        q[n // 2:].copy_(workloads.mix_keys_torch(torch.arange(n, n + n // 2, dtype=torch.int64, device=dev)))
+    _, mid = srv.submit_build(keys, vals, 77, stream=side)
+    v = torch.empty(n, dtype=torch.int32, device=dev)
+    f = torch.empty(n, dtype=torch.uint8, device=dev)
+    srv.submit_lookup(mid, q, v, f, stream=side)
+    srv.wait_all()
+    torch.cuda.synchronize()
+    h1, s1 = export_handle(fks, srv.map_handle(mid))
+    alone = fks.fks_build_u64(keys, vals, 77)
+    h2, s2, _ = fks.fks_export(alone)
+    assert (h1 == h2).all() and (s1 == s2).all()
+    want_v = torch.arange(n // 2, dtype=torch.int32, device=dev).flip(0)
+    assert bool(f[: n // 2].all()) and not bool(f[n // 2:].any())
+    assert torch.equal(v[: n // 2], want_v)
+    srv.destroy()
+
+
+def test_oversized_build_fails_without_evicting():
+    """A build whose reservation exceeds the whole budget completes with FKS_ENOMEM at once
+    and leaves the resident maps in place."""
+    import torch
+    fks, serve = _mods()
+    dev = torch.device("cuda:0")
+    announce("gpu serve: oversized build leaves resident maps alone")
+    n = 20000
+    per_map = 16 * ((n + 7) // 8) + 16 * 4 * n + 24 * 64 + 4096
+    srv = fks.FksServer(3 * per_map)
+    ids = []
+    for b in range(2):
+        k = workloads.mix_keys_torch(torch.arange(b * n, (b + 1) * n, dtype=torch.int64, device=dev))
+        v = torch.arange(n, dtype=torch.int32, device=dev)
+        ids.append(srv.submit_build(k, v, b + 1)[1])
+    srv.wait_all()
+    big = 5 * n
+    kb = workloads.mix_keys_torch(torch.arange(10 * n, 10 * n + big, dtype=torch.int64, device=dev))
+    vb = torch.arange(big, dtype=torch.int32, device=dev)
+    rid, _ = srv.submit_build(kb, vb, 9)
+    srv.wait_all()
+    done, status, _ = srv.poll(rid)
+    assert done and status == fks.FKS_ENOMEM
+    st = srv.stats()
+    assert st["evictions"] == 0 and st["resident_maps"] == 2
+    for mid in ids:
+        assert srv.map_handle(mid)
+    srv.destroy()

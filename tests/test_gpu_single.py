@@ -44,6 +44,9 @@ def assert_same_table(m, ref):
     assert inf["r"] == ref.r and inf["S"] == ref.S and inf["n"] == ref.n
     assert h.size == rh.size and (h == rh).all(), "header bytes differ"
     assert s.size == rs.size and (s == rs).all(), "cell bytes differ"
+    # the bucket-size histogram of fks_info counts the oracle's sizes of the n buckets
+    sizes = fkscheck.decode_header(rh, ref.n)[1][:ref.n] if ref.n else np.zeros(0, np.int64)
+    assert inf["size_hist"] == np.bincount(sizes, minlength=16).tolist()
 
 
 SIZES = [1, 2, 3, 7, 8, 9, 63, 255, 256, 257, 1000, 2047, 2048 * 8 + 5, 65536, 100003, (1 << 20) + 77]
@@ -135,9 +138,18 @@ def test_errors():
     with pytest.raises(fks.FksError) as e:
         gpu_build(keys, np.zeros(1000, np.uint32), 1)
     assert e.value.code == fks.FKS_EDUPKEY
+    # every attempt rejected (a bucket above 15 keys, or too many cells): repeated keys
+    # are reported as such, on both schedules, as the oracle reports them
+    for keys_r, kw in ((np.full(16, 9, np.uint64), {}), (np.full(16, 9, np.uint64), {"schedule": 1}),
+                       (np.repeat(workloads.unique_u64(300, 7), 10), {})):
+        with pytest.raises(oracle.OracleError) as eo:
+            oracle.build_u64(keys_r, np.zeros(keys_r.size, np.uint32), 1)
+        with pytest.raises(fks.FksError) as e:
+            gpu_build(keys_r, np.zeros(keys_r.size, np.uint32), 1, **kw)
+        assert e.value.code == fks.FKS_EDUPKEY == eo.value.code
     with pytest.raises(fks.FksError) as e:
-        gpu_build(np.full(16, 9, np.uint64), np.zeros(16, np.uint32), 1)
-    assert e.value.code == fks.FKS_EBUILD
+        fks.fks_build_u64_v64(to_dev(np.full(20, 3, np.uint64)), to_dev(np.zeros(20, np.uint64)), 1)
+    assert e.value.code == fks.FKS_EDUPKEY
     with pytest.raises(fks.FksError) as e:
         gpu_build(workloads.unique_u64(2000, 1), np.zeros(2000, np.uint32), 1, c=1)
     assert e.value.code == fks.FKS_EBUILD
@@ -369,10 +381,30 @@ def test_string_map_edge_cases():
     torch.cuda.synchronize()
     assert to_np(f, "u8").tolist() == [1] * 8 + [0] * 3
     assert to_np(v, "u32").tolist()[:8] == list(range(8))
+    # needle offsets that are not a range of the needle buffer are answered absent and
+    # nothing is read through them: a negative start, an end before the start, an end past
+    # the buffer; the well-formed needles around them are answered as usual
+    buf = np.frombuffer(b"abcabcd", np.uint8)
+    qo = np.array([0, 3, -5, 7, 2, 10**12, 3, 7], np.int64)
+    v = empty(qo.size - 1, "u32")
+    f = empty(qo.size - 1, "u8")
+    fks.fks_lookup_bytes(m, to_dev(qo), to_dev(buf), v, f, missing=MISSING)
+    torch.cuda.synchronize()
+    assert to_np(f, "u8").tolist() == [1, 0, 0, 0, 0, 0, 1]
+    assert to_np(v, "u32").tolist() == [3, MISSING, MISSING, MISSING, MISSING, MISSING, 4]
     dup_off, dup_data = workloads.to_csr([b"alpha", b"beta", b"gamma", b"beta"])
     with pytest.raises(fks.FksError) as e:
         gpu_build_bytes(dup_off, dup_data, np.zeros(4, np.uint32), 1)
     assert e.value.code == fks.FKS_EDUPKEY
+    # sixteen copies of one string: every attempt is rejected for size, then the equal-key
+    # check reports them (strings equal on a prefix are not repeats)
+    rep_off, rep_data = workloads.to_csr([b"same"] * 16 + [b"sam", b"samee", b"other"])
+    with pytest.raises(fks.FksError) as e:
+        gpu_build_bytes(rep_off, rep_data, np.zeros(19, np.uint32), 1)
+    assert e.value.code == fks.FKS_EDUPKEY
+    pre_off, pre_data = workloads.to_csr([b"ab" * k for k in range(1, 17)])
+    pm = gpu_build_bytes(pre_off, pre_data, np.arange(16, dtype=np.uint32), 1)
+    assert_same_table(pm, oracle.build_bytes(pre_off, pre_data, np.arange(16, dtype=np.uint32), 1))
     bad = np.array([0, 5, 3, 9], np.int64)
     with pytest.raises(fks.FksError) as e:
         gpu_build_bytes(bad, np.zeros(9, np.uint8), np.zeros(3, np.uint32), 1)

@@ -156,9 +156,22 @@ def test_duplicate_keys_are_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.build_u64(np.array([5, 5], np.uint64), np.zeros(2, np.uint32), 1)
     assert e.value.code == oracle.EDUPKEY
-    # sixteen copies never fit a bucket: every attempt is rejected for size
+    # sixteen copies never fit a bucket: every attempt is rejected for size, and the
+    # rejected build reports the repeated key
     with pytest.raises(oracle.OracleError) as e:
         oracle.build_u64(np.full(16, 9, np.uint64), np.zeros(16, np.uint32), 1)
+    assert e.value.code == oracle.EDUPKEY
+    # ten copies of each of 300 keys fit the size field but need about 10n cells, so
+    # every attempt is rejected for space before any bucket is searched
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(np.repeat(_keys(300, 7), 10), np.zeros(3000, np.uint32), 1)
+    assert e.value.code == oracle.EDUPKEY
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64_v64(np.full(20, 3, np.uint64), np.zeros(20, np.uint64), 1)
+    assert e.value.code == oracle.EDUPKEY
+    # distinct keys that no attempt accepts stay a rejected build
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(_keys(2000, 6), np.zeros(2000, np.uint32), 1, c=1)
     assert e.value.code == oracle.EBUILD
 
 
@@ -249,6 +262,16 @@ def test_duplicate_strings_are_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.build_bytes(off, data, np.zeros(4, np.uint32), 1)
     assert e.value.code == oracle.EDUPKEY
+    # sixteen copies of one string overflow every attempt's bucket
+    off, data = workloads.to_csr([b"same"] * 16 + [b"other"])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_bytes(off, data, np.zeros(17, np.uint32), 1)
+    assert e.value.code == oracle.EDUPKEY
+    # sixteen distinct strings of one bucket's worth are not mistaken for repeats: the
+    # check compares bytes, so strings equal on a prefix or of other lengths differ
+    off, data = workloads.to_csr([b"ab" * k for k in range(1, 17)])
+    m = oracle.build_bytes(off, data, np.arange(16, dtype=np.uint32), 1)
+    assert m.info["n"] == 16
 
 
 def test_from_array_keeps_first_occurrence():
