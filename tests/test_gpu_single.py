@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2508_11443_amd import workloads
-from tests import fkscheck
+from tests import collide, fkscheck
 from tests.gpu_util import announce, empty, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
@@ -177,14 +177,12 @@ def test_bench_size_bit_exact():
     m = gpu_build(keys, vals, seed)
     ref = oracle.build_u64(keys, vals, seed)
     assert_same_table(m, ref)
-    q, expect = workloads.u64_queries(keys, n, 0.5, 2027)
+    q, expect, src = workloads.u64_queries(keys, n, 0.5, 2027, return_index=True)
     v, f = gpu_lookup(m, q)
     assert (f == expect).all()
     hit = expect == 1
-    # the value of a hit is the key's index; recover it through a sort of the keys
-    order = np.argsort(keys)
-    pos = np.searchsorted(keys, q[hit], sorter=order)
-    assert (v[hit] == order[pos].astype(np.uint32)).all()
+    # the value of a hit is the index of its key
+    assert (v[hit] == src[hit].astype(np.uint32)).all()
     assert (v[~hit] == MISSING).all()
     del m
     torch.cuda.empty_cache()
@@ -305,6 +303,29 @@ def test_string_map_bit_exact(n):
     rv, rf = ref.lookup_bytes(qo, qd, missing=MISSING)
     assert (to_np(f, "u8") == rf).all() and (rf == qf).all()
     assert (to_np(v, "u32") == rv).all()
+
+
+def test_fingerprint_collision_takes_the_next_attempt():
+    """Two distinct 16-byte strings whose fingerprints are equal under attempt 0's base share
+    a bucket no level-two trial can split: the GPU build must reject attempt 0 (the strings
+    differ, so this is no repeated key), take attempt 1 with its new base, and export the
+    oracle's bytes; every string, the two included, is found with its value."""
+    import torch
+    sigma = 0xC0111DE
+    announce(f"gpu single bytes: fingerprint collision under attempt 0, seed={sigma}")
+    for n_other in (3000, 1):
+        off, data, a, b = collide.strings_with_collision(sigma, n_other, 77)
+        n = off.size - 1
+        vals = np.arange(n, dtype=np.uint32)
+        ref = oracle.build_bytes(off, data, vals, sigma)
+        assert ref.r >= 1 and ref.info["rejected_exhausted"] >= 1
+        m = gpu_build_bytes(off, data, vals, sigma)
+        assert_same_table(m, ref)
+        v = empty(n, "u32")
+        f = empty(n, "u8")
+        _fks().fks_lookup_bytes(m, to_dev(off), to_dev(data), v, f, missing=MISSING)
+        torch.cuda.synchronize()
+        assert to_np(f, "u8").all() and (to_np(v, "u32") == vals).all()
 
 
 def test_string_bench_size_bit_exact():

@@ -17,7 +17,7 @@ import pytest
 import oracle
 from oracle import rounds, spec
 from paper_2508_11443_amd import workloads
-from tests import fkscheck
+from tests import collide, fkscheck
 
 
 def _keys(n, seed, dense=0.0):
@@ -272,6 +272,39 @@ def test_duplicate_strings_are_reported():
     off, data = workloads.to_csr([b"ab" * k for k in range(1, 17)])
     m = oracle.build_bytes(off, data, np.arange(16, dtype=np.uint32), 1)
     assert m.info["n"] == 16
+
+
+def test_fingerprint_collision_rejects_the_attempt():
+    """Two distinct strings whose fingerprints are equal under attempt 0's base (Section 3.1:
+    strings reach the integer construction through a hash) fall into one bucket that no
+    level-two trial can split.  The bucket is exhausted, its strings compare unequal, so
+    attempt 0 is rejected (not reported as a repeated key), and attempt 1's new base
+    separates them; lookups still answer every string, the colliding two included."""
+    sigma = 0xC0111DE
+    beta0, beta1 = spec.level1_consts(sigma, 0)[3], spec.level1_consts(sigma, 1)[3]
+    assert oracle.level1_consts(sigma, 0)[3] == beta0
+    off, data, a, b = collide.strings_with_collision(sigma, 3000, 77)
+    # equal under beta0 by the pure-Python fingerprint and the oracle's, unequal under beta1
+    assert spec.fingerprint(a, beta0) == spec.fingerprint(b, beta0)
+    assert oracle.fingerprint(a, beta0) == oracle.fingerprint(b, beta0) == spec.fingerprint(a, beta0)
+    assert spec.fingerprint(a, beta1) != spec.fingerprint(b, beta1)
+    n = off.size - 1
+    vals = np.arange(n, dtype=np.uint32)
+    m = oracle.build_bytes(off, data, vals, sigma)
+    assert m.r == 1
+    assert m.info["rejected_exhausted"] == 1
+    assert m.info["rejected_size"] == 0 and m.info["rejected_space"] == 0
+    strings = workloads.from_csr(off, data)
+    y = np.array([spec.fingerprint(x, beta1) for x in strings], np.uint64)
+    fkscheck.check_table(y, vals, sigma, 1, *m.export(), aux=vals)
+    v, f = m.lookup_bytes(off, data)
+    assert f.all() and (v == vals).all()
+    # the pair alone (plus one other string) takes the same path
+    o2, d2 = workloads.to_csr([a, b"zz", b])
+    m2 = oracle.build_bytes(o2, d2, np.array([5, 6, 7], np.uint32), sigma)
+    assert m2.r >= 1 and m2.info["rejected_exhausted"] >= 1
+    v2, f2 = m2.lookup_bytes(o2, d2)
+    assert f2.all() and list(v2) == [5, 6, 7]
 
 
 def test_from_array_keeps_first_occurrence():
