@@ -86,9 +86,8 @@ def bench_inputs():
     n = 1 << 26
     keys = workloads.unique_u64(n, 2026, dense_fraction=0.5)
     order = np.argsort(keys, kind="stable")
-    q, expect = workloads.u64_queries(keys, n, 0.5, 2027)
-    hit = expect == 1
-    return keys, order, q, expect, np.searchsorted(keys, q[hit], sorter=order)
+    q, expect, src = workloads.u64_queries(keys, n, 0.5, 2027, return_index=True)
+    return keys, order, q, expect, src
 
 
 @pytest.mark.parametrize("layout", [0, 1])
@@ -98,7 +97,7 @@ def test_bench_size(layout, bench_inputs):
     Eytzinger layout must be that array gathered in level order; 2^26 needles at
     50% hits against dictionary semantics."""
     import torch
-    keys, order, q, expect, pos = bench_inputs
+    keys, order, q, expect, src = bench_inputs
     n = keys.size
     announce(f"gpu search: bench size layout={layout}")
     vals = np.arange(n, dtype=np.uint32)
@@ -117,7 +116,7 @@ def test_bench_size(layout, bench_inputs):
     v, f = gpu_lookup(s, q)
     assert (f == expect).all()
     hit = expect == 1
-    assert (v[hit] == order[pos].astype(np.uint32)).all()
+    assert (v[hit] == src[hit].astype(np.uint32)).all()
     assert (v[~hit] == MISSING).all()
     del s
     torch.cuda.empty_cache()
