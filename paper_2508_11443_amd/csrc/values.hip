@@ -19,7 +19,7 @@
 namespace fks {
 
 constexpr int kVBlock = 256;
-constexpr uint32_t kVPartials = 65536;  // most workgroups of the reduction's first pass (one group per lane up to 2^27 keys)
+constexpr uint32_t kVGrid = 4096;   // most workgroups of the reduction's first pass (16 per CU; they stride beyond)
 
 
 __device__ __forceinline__ uint64_t cell_value(const Cell& c, bool v64) {
@@ -86,33 +86,51 @@ __device__ __forceinline__ uint64_t block_fold(uint64_t v, uint32_t op, uint64_t
     return red[0];
 }
 
-// first pass: one group of eight buckets per lane; each bucket's s^2 cells are
-// tested against the bucket's level-two hash and its own keys folded in
+// first pass: consecutive cells on consecutive lanes, kRCells per lane per round, so a
+// wave's loads cover 64 consecutive cells (1 KiB).  Each lane recomputes its key's bucket
+// (the level-one hash) and the cell the key hashes to from the bucket's group record;
+// cells of neighbouring lanes belong to neighbouring buckets, so those records are mostly
+// one or two cache lines per wave.  A cell holds its own key exactly when that cell is the
+// lane's own; a fill copy of a bucket's lowest key sits elsewhere and is skipped.
+constexpr uint32_t kRCells = 4;
+
 template <bool V64>
-__global__ __launch_bounds__(kVBlock) void k_reduce_groups(const Group* __restrict__ header,
-                                                             const Cell* __restrict__ slots, uint64_t G, uint64_t S,
-                                                             const Triple* __restrict__ Cg, uint32_t T, uint32_t op,
-                                                             uint64_t ident, uint64_t* __restrict__ partial) {
+__global__ __launch_bounds__(kVBlock) void k_reduce_cells(const Group* __restrict__ header,
+                                                            const Cell* __restrict__ slots, uint64_t S, Triple A,
+                                                            uint64_t magic, uint32_t n,
+                                                            const Triple* __restrict__ Cg, uint32_t T, uint32_t op,
+                                                            uint64_t ident, uint64_t* __restrict__ partial) {
     __shared__ Triple C[kTMax];
     __shared__ uint64_t red[kVBlock];
     for (uint32_t k = threadIdx.x; k < T; k += kVBlock) C[k] = Cg[k];
     __syncthreads();
     uint64_t acc = ident;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        const Group h = header[g];
-        for (uint32_t k = 0; k < 8; ++k) {
-            const uint32_t s = nib(h.sizes, k);
-            const uint32_t t = group_t(h, k);
+    const uint64_t step = (uint64_t)gridDim.x * kVBlock * kRCells;
+    for (uint64_t base = (uint64_t)blockIdx.x * kVBlock * kRCells; base < S; base += step) {
+        Cell x[kRCells];
+#pragma unroll
+        for (uint32_t k = 0; k < kRCells; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
+            x[k] = i < S ? slots[i] : Cell{0, 0, 0};
+        }
+        uint32_t j[kRCells];
+        Group h[kRCells];
+#pragma unroll
+        for (uint32_t k = 0; k < kRCells; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
+            j[k] = fastmod(mshash(A, x[k].key), magic, n);
+            h[k] = i < S ? header[j[k] >> 3] : Group{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kRCells; ++k) {
+            const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
+            const uint32_t b = j[k] & 7u;
+            const uint32_t s = nib(h[k].sizes, b);
+            const uint32_t t = group_t(h[k], b);
             if (s == 0 || t >= T) continue;
             const uint32_t s2 = s * s;
-            const uint64_t start = (uint64_t)h.base + prefix_sq(h.sizes, k);
-            if (start + s2 > S) continue;
-            const Triple c = C[t];
-            for (uint32_t l = 0; l < s2; ++l) {
-                const Cell x = slots[start + l];
-                if (mshash(c, x.key) % s2 == l) acc = combine(op, acc, cell_value(x, V64));
-            }
+            const uint64_t own = (uint64_t)h[k].base + prefix_sq(h[k].sizes, b) + mshash(C[t], x[k].key) % s2;
+            if (own == i) acc = combine(op, acc, cell_value(x[k], V64));
         }
     }
     const uint64_t r = block_fold(acc, op, red);
@@ -210,9 +228,9 @@ namespace fks {
 
 // workgroups of the reduction's first pass (each strides over the table beyond that)
 static uint32_t reduce_partials(const fks_map* map) {
-    const uint64_t G = (map->n + 7) / 8;
-    uint64_t np = (G + kVBlock - 1) / kVBlock;
-    return (uint32_t)(np > kVPartials ? kVPartials : np);
+    const uint64_t per = (uint64_t)kVBlock * kRCells;
+    uint64_t np = (map->S + per - 1) / per;
+    return (uint32_t)(np > kVGrid ? kVGrid : np);
 }
 
 // the two passes of the reduction into `partial` (room for reduce_partials(map) entries)
@@ -225,14 +243,15 @@ static int reduce_launch(const fks_map* map, uint32_t op, uint64_t* d_out, uint6
     if (G == 0) {
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, nullptr, 0u, op, ident, d_out);
     } else {
+        const uint32_t n32 = (uint32_t)map->n;
         if (v64)
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_groups<true>, np, kVBlock, 0, st, map->header, map->slots, G,
-                                         map->S, map->C, map->T, op, ident, partial));
+                      hipLaunchKernelGGL(k_reduce_cells<true>, np, kVBlock, 0, st, map->header, map->slots, map->S,
+                                         map->A, map->magic_n, n32, map->C, map->T, op, ident, partial));
         else
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_groups<false>, np, kVBlock, 0, st, map->header, map->slots, G,
-                                         map->S, map->C, map->T, op, ident, partial));
+                      hipLaunchKernelGGL(k_reduce_cells<false>, np, kVBlock, 0, st, map->header, map->slots, map->S,
+                                         map->A, map->magic_n, n32, map->C, map->T, op, ident, partial));
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, partial, np, op, ident, d_out);
     }
     const hipError_t e = hipGetLastError();
@@ -253,3 +272,4 @@ extern "C" int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_ou
     dev_free(partial, st);
     return rc;
 }
+
