@@ -264,6 +264,21 @@ int fks_map_values(const fks_map* map, uint32_t op, uint64_t a, uint64_t b, cons
                    uint64_t table_len, const fks_allocator* alloc, void* stream, fks_map** out);
 int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream);
 
+/* fks_reduce_values_noalloc: fks_reduce_values for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors; it
+ * calls no allocator.  The partial folds of its first pass live in a static
+ * device array of 4096 uint64 (32 KiB) that each device keeps from its first
+ * call until the process ends; the first pass never has more workgroups than
+ * that, for every map size, so no map is refused for size.  Nothing in the
+ * array needs to start at zero: every partial is written before it is read.
+ * Every call on one device shares the array, so two calls whose kernels
+ * overlap on that device (on different streams, or from different host
+ * threads without ordering between their streams) race and may return wrong
+ * folds; calls ordered on one stream do not.  The first call on a device looks
+ * up the array's address (hipGetSymbolAddress) and can fail with FKS_EHIP.  */
+int fks_reduce_values_noalloc(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream);
+
 
 /* Sizes and build outcome of a map.  The bucket-size histogram is counted by
    one small kernel over the group headers, on the null stream, which the call

@@ -13,6 +13,8 @@
 // table in address order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fks_internal.hpp"
 #include "prof.hpp"
 
@@ -273,3 +275,42 @@ extern "C" int fks_reduce_values(const fks_map* map, uint32_t op, uint64_t* d_ou
     return rc;
 }
 
+// ---- reduction without allocation --------------------------------------------
+namespace fks {
+
+// The first pass's partial folds for fks_reduce_values_noalloc: at most kVGrid of them,
+// whatever the map's size.  Every device the library runs on holds its own copy for the
+// life of the process; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) uint64_t scratch[kVGrid];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint64_t* g_scratch[kMaxDevices];
+
+// device address of `scratch` on the current device, looked up once per device
+static int scratch_on_current_device(uint64_t** out) {
+    int dev = 0;
+    FKS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return FKS_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        FKS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[dev] = (uint64_t*)p;
+    }
+    *out = g_scratch[dev];
+    return FKS_OK;
+}
+
+}  // namespace fks
+
+extern "C" int fks_reduce_values_noalloc(const fks_map* map, uint32_t op, uint64_t* d_out, void* stream) {
+    if (!map || !d_out || op > FKS_VRED_XOR) return FKS_EINVAL;
+    // the first pass never has more than kVGrid workgroups; a larger need would be a bug
+    if (reduce_partials(map) > kVGrid) return FKS_EINVAL;
+    uint64_t* partial = nullptr;
+    const int rc = scratch_on_current_device(&partial);
+    if (rc != FKS_OK) return rc;
+    return reduce_launch(map, op, d_out, partial, (hipStream_t)stream);
+}

@@ -98,6 +98,16 @@ def torch_allocator(device=None) -> Allocator:
     return Allocator(alloc, free)
 
 
+def fks_reduce_values_noalloc(m: FksMap, op: int, out, stream=None):
+    """fks_reduce_values into out (a one-element int64/uint64 device tensor) without any
+    allocation: the library's static per-device scratch holds the partial folds.  Calls
+    that overlap on one device race for that scratch.  Asynchronous; returns out."""
+    _fits(1, out=out)
+    rc = _load().fks_reduce_values_noalloc(m.handle, op, _dev(out, _u64_types(), "out"), _stream(stream))
+    _check(rc, "fks_reduce_values_noalloc")
+    return out
+
+
 def _alloc_arg(allocator):
     return None if allocator is None else allocator.pointer()
 
@@ -120,6 +130,7 @@ SIGNATURES = [
     ("fks_info", _I32, [_VP, _VP]),
     ("fks_map_values", _I32, [_VP, _U32, _U64, _U64, _VP, _U64, _VP, _VP, ctypes.POINTER(_VP)]),
     ("fks_reduce_values", _I32, [_VP, _U32, _VP, _VP]),
+    ("fks_reduce_values_noalloc", _I32, [_VP, _U32, _VP, _VP]),
     ("fks_export", _I32, [_VP, _VP, _VP, _VP]),
     ("fks_destroy", None, [_VP]),
     ("fks_strerror", ctypes.c_char_p, [_I32]),
