@@ -33,7 +33,11 @@
  *     reproduces byte for byte):
  *       header: ceil(n/8) records of 16 bytes, one per group of 8 buckets:
  *               u32 slot base of the group, u32 sizes (4 bits per bucket,
- *               bucket 8g+k in bits 4k..4k+3), u8 trial index t[8];
+ *               bucket 8g+k in bits 4k..4k+3), u8 t[8]: the trial index of
+ *               a bucket of two or more keys; for a bucket of one key (whose
+ *               trial is always 0) the top 8 bits of that key's trial-0
+ *               level-two hash, a tag that lets a lookup answer "absent"
+ *               without reading the cell; 0 for an empty bucket;
  *       cells : S records of 16 bytes: u64 key, u32 value, u32 aux
  *               (aux = 0 for integer keys, the key's index for string keys;
  *               the key word of a string map is the string's fingerprint).

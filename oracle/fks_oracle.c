@@ -50,6 +50,11 @@
  *   R7 table layout: 16-byte header per group of eight buckets
  *      {u32 slot base of the group, u32 sizes (4 bits per bucket), u8 t[8]}
  *      and 16-byte cells {u64 key, u32 value, u32 aux}.
+ *   R8 a bucket of one key always takes trial 0 (one key cannot collide), so
+ *      its trial byte holds a tag of that key instead: the top 8 bits of its
+ *      trial-0 level-two hash.  A lookup may answer "absent" when a needle's
+ *      tag differs, without reading the cell; the membership test itself is
+ *      unchanged.  Empty buckets keep 0.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -105,6 +110,14 @@ void oracle_level2_consts(uint64_t sigma, uint32_t r, uint32_t t, uint64_t out[3
     out[0] = oracle_splitmix(sigma, base + 0);
     out[1] = oracle_splitmix(sigma, base + 1);
     out[2] = oracle_splitmix(sigma, base + 2);
+}
+
+/* ---- R8: tag of a one-key bucket ------------------------------------------ */
+
+/* The top 8 bits of the key's trial-0 level-two hash (C points at the attempt's triples). */
+static uint8_t or_tag(const uint64_t* C, uint64_t x)
+{
+    return (uint8_t)(oracle_hash(C[0], C[1], C[2], x) >> 24);
 }
 
 /* ---- R6: string fingerprint -------------------------------------------- */
@@ -282,7 +295,8 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
             uint64_t j = 8 * gi + k;
             if (j < n) {
                 sizes |= (uint32_t)shape[j] << (4 * k);
-                header[16 * gi + 8 + k] = tvals[j];
+                /* R8: a bucket of one key stores its key's tag where the trial would be */
+                header[16 * gi + 8 + k] = shape[j] == 1 ? or_tag(C, keyv[members[gstart[j]]]) : tvals[j];
             }
         }
         or_put_u32(header + 16 * gi, (uint32_t)offsets[8 * gi]);
@@ -568,7 +582,7 @@ static int64_t or_probe(const oracle_map* M, uint64_t x)
         uint32_t si = (sizes >> (4 * i)) & 15u;
         off += (uint64_t)si * si;
     }
-    uint32_t t = h[8 + k];
+    uint32_t t = s == 1 ? 0 : h[8 + k];   /* R8: a one-key bucket's byte is its tag; its trial is 0 */
     const uint64_t* C = M->C + 3 * (uint64_t)t;
     return (int64_t)(off + oracle_hash(C[0], C[1], C[2], x) % (s * s));
 }

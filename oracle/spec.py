@@ -64,11 +64,16 @@ def fingerprint(data: bytes, beta: int) -> int:
     return acc
 
 
+def tag(c0, x: int) -> int:
+    """Tag of the key of a one-key bucket: the top 8 bits of its trial-0 level-two hash."""
+    return hash32(*c0, x) >> 24
+
+
 def build_small(keys, vals, sigma, c=4, T=64, R=16):
     """make_1 / make_2 on Python lists (tiny n).  Returns a dict or raises ValueError(code)."""
     n = len(keys)
     if n == 0:
-        return dict(n=0, S=0, r=0, sizes=[], t=[], offsets=[0], cells=[])
+        return dict(n=0, S=0, r=0, sizes=[], t=[], tbyte=[], offsets=[0], cells=[])
     for r in range(R):
         a0, a1, b, _ = level1_consts(sigma, r)
         g = [hash32(a0, a1, b, x) % n for x in keys]
@@ -118,13 +123,19 @@ def build_small(keys, vals, sigma, c=4, T=64, R=16):
             for p in range(lo, hi):
                 if cells[p] is None:
                     cells[p] = cells[occ[0]]
-        return dict(n=n, S=S, r=r, sizes=sizes, t=tj, offsets=offsets, cells=cells,
+        # the header byte of a bucket: its trial, or for a bucket of one key that key's tag
+        tbyte = list(tj)
+        for j in range(n):
+            if sizes[j] == 1:
+                tbyte[j] = tag(C[0], keys[groups[j][0]])
+        return dict(n=n, S=S, r=r, sizes=sizes, t=tj, tbyte=tbyte, offsets=offsets, cells=cells,
                     a=(a0, a1, b), C=C)
     raise ValueError("EBUILD")
 
 
 def pack_header(sizes, t):
-    """The 16-byte group records for bucket sizes and trial indices."""
+    """The 16-byte group records for bucket sizes and header bytes (trial indices, and the
+    tags of one-key buckets)."""
     n = len(sizes)
     out = bytearray()
     base = 0

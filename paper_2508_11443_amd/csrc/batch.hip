@@ -315,6 +315,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                 uint32_t t = 0;
                 bool exhausted = false;
                 const Cell* bk = grouped_s + ko + kst;
+                uint64_t key0 = 0;   // the key of a one-key bucket
                 if (fast) {
                     // this chunk's records come from the window prefetched at K0
                     if (tid < K1 - K0) L.ent[tid] = pre0;
@@ -328,6 +329,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                     }
                     if (s == 1) {
                         L.smap[lz] = (uint16_t)lk;   // a lone key owns its bucket's one cell
+                        key0 = L.ent[lk].key;
                     } else if (s >= 2 && s <= 8 && !exhausted) {
                         // the cells of every key from registers; each cell is written once, the
                         // empty ones with the key of the lowest occupied cell (fill rule)
@@ -382,6 +384,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                         t = first_trial(L.C, T, s, L.mag[s], [&](uint32_t i) { return bk[i].key; });
                         exhausted = t == T;
                     }
+                    if (s == 1) key0 = bk[0].key;
                     const uint32_t s2 = s * s;
                     if (s >= 1 && !exhausted) {
                         const Triple cc = L.C[t];
@@ -410,7 +413,8 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                 }
                 if (exhausted) t = 0;
                 if (t) atomicMax(&L.max_t, t);
-                reinterpret_cast<uint8_t*>(L.tsh)[tid] = (uint8_t)t;
+                // a one-key bucket's byte is its key's tag (its trial is 0)
+                reinterpret_cast<uint8_t*>(L.tsh)[tid] = (uint8_t)(s == 1 ? key_tag(L.C[0], key0) : t);
                 __syncthreads();
                 if (tid < BT / 8) {
                     const uint32_t gg = b0 / 8 + tid;
@@ -539,11 +543,9 @@ __global__ __launch_bounds__(256) void k_batch_lookup(const LDesc* __restrict__ 
         Cell cl[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            if (s[k]) {
-                const Triple cc = Cpool[(uint64_t)id[k] * d[k].T + group_t(h[k], kk[k])];
-                const uint32_t p = h[k].base + prefix_sq(h[k].sizes, kk[k]) + mshash(cc, x[k]) % (s[k] * s[k]);
-                cl[k] = slot_pool[d[k].slot_off + p];
-            }
+            uint32_t p;
+            if (s[k]) s[k] = cell_of(h[k], kk[k], Cpool + (uint64_t)id[k] * d[k].T, x[k], p) ? 1u : 0u;
+            if (s[k]) cl[k] = slot_pool[d[k].slot_off + p];
         }
 #pragma unroll
         for (int k = 0; k < Q; ++k) {

@@ -28,8 +28,8 @@ struct Triple {
 struct alignas(16) Group {
     uint32_t base;    // first cell of the group
     uint32_t sizes;   // 4 bits per bucket
-    uint32_t t_lo;    // trial index of buckets 0..3 (one byte each)
-    uint32_t t_hi;    // trial index of buckets 4..7
+    uint32_t t_lo;    // trial index of buckets 0..3 (one byte each; a one-key bucket's byte is its key's tag)
+    uint32_t t_hi;    // the same for buckets 4..7
 };
 
 // 16-byte cell.
@@ -204,6 +204,24 @@ __host__ __device__ inline uint32_t prefix_cnt(uint32_t sizes, uint32_t k) {
 __host__ __device__ inline uint32_t group_t(const Group& g, uint32_t k) {
     uint32_t w = k < 4 ? g.t_lo : g.t_hi;
     return (w >> (8 * (k & 3))) & 0xFFu;
+}
+
+// A bucket of one key always takes trial 0, so its trial byte holds a tag of that key
+// instead: the top 8 bits of the key's trial-0 level-two hash (c0 = the first triple).
+__host__ __device__ inline uint32_t key_tag(const Triple& c0, uint64_t x) { return mshash(c0, x) >> 24; }
+
+// The cell needle x would occupy in bucket k of group record h, with the level-two
+// triples C of the map.  False when x cannot be in the bucket: the bucket is empty, or it
+// holds one key whose tag differs from x's (no cell is read then).  A true result still
+// needs the key comparison of the membership test.
+__host__ __device__ inline bool cell_of(const Group& h, uint32_t k, const Triple* C, uint64_t x, uint32_t& cell) {
+    const uint32_t s = nib(h.sizes, k);
+    if (s == 0) return false;
+    const uint32_t tb = group_t(h, k);
+    const uint32_t hv = mshash(C[s == 1 ? 0u : tb], x);
+    if (s == 1 && (hv >> 24) != tb) return false;
+    cell = h.base + prefix_sq(h.sizes, k) + (s == 1 ? 0u : hv % (s * s));
+    return true;
 }
 
 }  // namespace fks

@@ -63,15 +63,10 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
         uint32_t s[kQ];
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
-            s[k] = nib(h[k].sizes, kk[k]);
-            if (s[k]) {
-                const uint32_t s2 = s[k] * s[k];
-                const uint32_t p = h[k].base + prefix_sq(h[k].sizes, kk[k]) +
-                                   mshash(C[group_t(h[k], kk[k])], x[k]) % s2;
-                c[k] = slots[p];
-            } else {
-                c[k] = Cell{~x[k], 0, 0};
-            }
+            uint32_t p;
+            s[k] = cell_of(h[k], kk[k], C, x[k], p) ? 1u : 0u;
+            if (s[k]) c[k] = slots[p];
+            else c[k] = Cell{~x[k], 0, 0};
         }
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
@@ -116,11 +111,10 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
         const uint32_t j = fastmod(mshash(A, y), magic, n);
         const Group h = header[j >> 3];
         const uint32_t k = j & 7u;
-        const uint32_t sz = nib(h.sizes, k);
         bool hit = false;
         uint32_t v = missing;
-        if (sz) {
-            const uint32_t p = h.base + prefix_sq(h.sizes, k) + mshash(C[group_t(h, k)], y) % (sz * sz);
+        uint32_t p;
+        if (cell_of(h, k, C, y, p)) {
             const Cell c = slots[p];
             if (c.key == y) {
                 const int64_t ka = koff[c.aux], kb = koff[c.aux + 1];

@@ -624,6 +624,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 c0k[k] = off;
                 if (s == 1) {
                     L.smap[off] = (uint16_t)i;
+                    L.tb[lb] = (uint8_t)key_tag(LC[0], xk[k]);   // trial 0; the byte holds the key's tag
                 } else {
                     if (!given_t) {
                         const uint32_t cell = off + fastmod(mshash(LC[0], xk[k]), L.mag[s], s * s);
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 t = 0;
             }
             if (t) atomicMax(&L.flags[2], t);
-            L.tb[b] = (uint8_t)t;
+            L.tb[b] = (uint8_t)(s == 1 ? key_tag(LC[0], mine[0]) : t);
         }
         __syncthreads();
     }

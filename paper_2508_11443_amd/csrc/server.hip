@@ -93,11 +93,9 @@ __global__ __launch_bounds__(256) void k_lookup_multi(const LTab* __restrict__ t
         Cell c[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (s[k]) {
-                const uint32_t p = h[k].base + prefix_sq(h[k].sizes, kk[k]) +
-                                   mshash(C[group_t(h[k], kk[k])], x[k]) % (s[k] * s[k]);
-                c[k] = R.slots[p];
-            }
+            uint32_t p;
+            if (s[k]) s[k] = cell_of(h[k], kk[k], C, x[k], p) ? 1u : 0u;
+            if (s[k]) c[k] = R.slots[p];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {

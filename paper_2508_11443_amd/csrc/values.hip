@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kVBlock) void k_reduce_cells(const Group* __restric
             const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
             const uint32_t b = j[k] & 7u;
             const uint32_t s = nib(h[k].sizes, b);
-            const uint32_t t = group_t(h[k], b);
+            const uint32_t t = s == 1 ? 0u : group_t(h[k], b);   // a one-key bucket's byte is a tag
             if (s == 0 || t >= T) continue;
             const uint32_t s2 = s * s;
             const uint64_t own = (uint64_t)h[k].base + prefix_sq(h[k].sizes, b) + mshash(C[t], x[k].key) % s2;

@@ -19,6 +19,19 @@ from oracle import rounds, spec
 
 
 def decode_header(header: np.ndarray, n: int):
+    """(group bases, bucket sizes, bucket trials).  A bucket of at most one key has trial 0:
+    the byte of a one-key bucket is its key's tag (decode_tags)."""
+    base, sizes, tbytes = _decode(header, n)
+    return base, sizes, np.where(sizes >= 2, tbytes, 0)
+
+
+def decode_tags(header: np.ndarray, n: int):
+    """The raw per-bucket header bytes: the trial of a bucket of two or more keys, the tag of
+    a one-key bucket's key, 0 for an empty bucket."""
+    return _decode(header, n)[2]
+
+
+def _decode(header, n):
     h = np.asarray(header, np.uint8).reshape(-1, 16)
     ng = (n + 7) // 8
     assert h.shape[0] == ng, (h.shape, ng)
@@ -26,8 +39,8 @@ def decode_header(header: np.ndarray, n: int):
     packed = h[:, 4:8].copy().view(np.uint32).ravel().astype(np.int64)
     shifts = 4 * np.arange(8, dtype=np.int64)
     sizes = ((packed[:, None] >> shifts[None, :]) & 15).ravel()
-    tvals = h[:, 8:16].astype(np.int64).ravel()
-    return base, sizes, tvals
+    tbytes = h[:, 8:16].astype(np.int64).ravel()
+    return base, sizes, tbytes
 
 
 def decode_cells(slots: np.ndarray):
@@ -45,9 +58,11 @@ def check_table(keyv: np.ndarray, vals: np.ndarray, sigma: int, r: int, header, 
     keyv = np.asarray(keyv, np.uint64)
     n = keyv.size
     base, sizes_all, t_all = decode_header(header, n)
+    raw_all = decode_tags(header, n)
     S = int(np.asarray(slots).size // 16)
     sizes, tv = sizes_all[:n], t_all[:n]
-    assert (sizes_all[n:] == 0).all() and (t_all[n:] == 0).all(), "padding buckets not zero"
+    assert (sizes_all[n:] == 0).all() and (raw_all[n:] == 0).all(), "padding buckets not zero"
+    assert (raw_all[:n][sizes == 0] == 0).all(), "an empty bucket's header byte is not zero"
     a0, a1, b, _ = spec.level1_consts(sigma, r)
     g = rounds.hash_vec(a0, a1, b, keyv) % n
     counts = np.bincount(g, minlength=n)
@@ -69,6 +84,12 @@ def check_table(keyv: np.ndarray, vals: np.ndarray, sigma: int, r: int, header, 
         a0t, a1t, bt = (int(v) for v in C[t])
         h[sel] = rounds.hash_vec(a0t, a1t, bt, keyv[sel]) % sq[g[sel]]
     pos = offs[g] + h
+    # the byte of a one-key bucket is its key's tag: the top 8 bits of the trial-0 hash
+    one = sizes[g] == 1
+    if one.any():
+        a0t, a1t, bt = (int(v) for v in C[0])
+        tags = (rounds.hash_vec(a0t, a1t, bt, keyv[one]) >> 24).astype(np.int64)
+        assert (raw_all[g[one]] == tags).all(), "a one-key bucket's tag is not its key's"
     assert ((pos >= 0) & (pos < S)).all(), "not well formed"
     assert np.unique(pos).size == n, "not collision free"
     ck, cv, ca = decode_cells(slots)

@@ -33,7 +33,7 @@ def test_matches_python_restatement_bytewise(n):
         ref = spec.build_small([int(k) for k in keys], [int(v) for v in vals], sigma)
         h, s = m.export()
         assert (m.r, m.S) == (ref["r"], ref["S"])
-        assert h.tobytes() == spec.pack_header(ref["sizes"], ref["t"])
+        assert h.tobytes() == spec.pack_header(ref["sizes"], ref["tbyte"])
         assert s.tobytes() == spec.pack_cells(ref["cells"])
 
 

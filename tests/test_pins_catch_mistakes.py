@@ -165,7 +165,47 @@ def _mut_sizes_shifted(h, s, n):
     return hh.ravel(), s
 
 
+def _mut_tags_zero(h, s, n):
+    # a one-key bucket's byte left at its trial (0) instead of its key's tag
+    hh = h.reshape(-1, 16).copy()
+    _, sizes, _ = fkscheck.decode_header(h, n)
+    one = np.nonzero(sizes[:n] == 1)[0]
+    hh[one // 8, 8 + one % 8] = 0
+    return hh.ravel(), s
+
+
+def _mut_tag_of_trial_one(h, s, n):
+    # the tag taken from trial 1's hash instead of trial 0's
+    keys, vals, sigma, r, _, _ = _table()
+    hh = h.reshape(-1, 16).copy()
+    _, sizes, _ = fkscheck.decode_header(h, n)
+    a0, a1, b, _ = spec.level1_consts(sigma, r)
+    C1 = spec.level2_consts(sigma, r, 1)
+    for k in keys:
+        j = spec.hash32(a0, a1, b, int(k)) % n
+        if sizes[j] == 1:
+            hh[j // 8, 8 + j % 8] = spec.hash32(*C1, int(k)) >> 24
+    return hh.ravel(), s
+
+
+def _mut_tag_low_bits(h, s, n):
+    # the low 8 bits of the trial-0 hash instead of the top 8
+    keys, vals, sigma, r, _, _ = _table()
+    hh = h.reshape(-1, 16).copy()
+    _, sizes, _ = fkscheck.decode_header(h, n)
+    a0, a1, b, _ = spec.level1_consts(sigma, r)
+    C0 = spec.level2_consts(sigma, r, 0)
+    for k in keys:
+        j = spec.hash32(a0, a1, b, int(k)) % n
+        if sizes[j] == 1:
+            hh[j // 8, 8 + j % 8] = spec.hash32(*C0, int(k)) & 0xFF
+    return hh.ravel(), s
+
+
 TABLE_MUTANTS = {
+    "one-key bucket without its tag": _mut_tags_zero,
+    "tag from trial 1": _mut_tag_of_trial_one,
+    "tag from the low bits": _mut_tag_low_bits,
     "inclusive presum for bases": _mut_inclusive_base,
     "trial index off by one": _mut_t_plus_one,
     "non-minimal trial": _mut_t_not_minimal,
