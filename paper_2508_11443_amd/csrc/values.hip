@@ -88,55 +88,90 @@ __device__ __forceinline__ uint64_t block_fold(uint64_t v, uint32_t op, uint64_t
     return red[0];
 }
 
-// first pass: consecutive cells on consecutive lanes, kRCells per lane per round, so a
-// wave's loads cover 64 consecutive cells (1 KiB).  Each lane recomputes its key's bucket
-// (the level-one hash) and the cell the key hashes to from the bucket's group record;
-// cells of neighbouring lanes belong to neighbouring buckets, so those records are mostly
-// one or two cache lines per wave.  A cell holds its own key exactly when that cell is the
-// lane's own; a fill copy of a bucket's lowest key sits elsewhere and is skipped.
-constexpr uint32_t kRCells = 4;
+// first pass: each workgroup takes ranges of kVBlock consecutive groups (one group record
+// per lane, staged in LDS with an LDS map from each of the range's cells to its bucket),
+// then streams the range's cells, consecutive cells on consecutive lanes.  A cell holds its
+// own key exactly when the key's level-two hash in the cell's bucket lands on the cell; a
+// fill copy of a bucket's lowest key sits elsewhere and is skipped, so each key is folded
+// once.  A range with more cells than the LDS map holds (far beyond the ~15 cells of eight
+// buckets of random keys) is walked bucket by bucket instead.
+constexpr uint32_t kRMapCells = 8192;   // cells of one range mapped in LDS
+constexpr uint32_t kRUnroll = 4;        // cells per lane in flight
 
 template <bool V64>
-__global__ __launch_bounds__(kVBlock) void k_reduce_cells(const Group* __restrict__ header,
-                                                            const Cell* __restrict__ slots, uint64_t S, Triple A,
-                                                            uint64_t magic, uint32_t n,
-                                                            const Triple* __restrict__ Cg, uint32_t T, uint32_t op,
-                                                            uint64_t ident, uint64_t* __restrict__ partial) {
+__global__ __launch_bounds__(kVBlock) void k_reduce_ranges(const Group* __restrict__ header,
+                                                             const Cell* __restrict__ slots, uint64_t G, uint64_t S,
+                                                             const Triple* __restrict__ Cg, uint32_t T, uint32_t op,
+                                                             uint64_t ident, uint64_t* __restrict__ partial) {
     __shared__ Triple C[kTMax];
+    __shared__ Group rec[kVBlock];
+    __shared__ uint16_t owner[kRMapCells];   // (group in the range << 3) | bucket
+    __shared__ uint64_t mag[16];
     __shared__ uint64_t red[kVBlock];
-    for (uint32_t k = threadIdx.x; k < T; k += kVBlock) C[k] = Cg[k];
-    __syncthreads();
+    __shared__ uint32_t span[2];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t k = tid; k < T; k += kVBlock) C[k] = Cg[k];
+    if (tid < 16) mag[tid] = tid ? fastmod_magic(tid * tid) : 0;
     uint64_t acc = ident;
-    const uint64_t step = (uint64_t)gridDim.x * kVBlock * kRCells;
-    for (uint64_t base = (uint64_t)blockIdx.x * kVBlock * kRCells; base < S; base += step) {
-        Cell x[kRCells];
+    for (uint64_t g0 = (uint64_t)blockIdx.x * kVBlock; g0 < G; g0 += (uint64_t)gridDim.x * kVBlock) {
+        const uint32_t ng = (uint32_t)min((uint64_t)kVBlock, G - g0);
+        __syncthreads();   // the previous range's LDS is no longer read
+        Group h{0, 0, 0, 0};
+        if (tid < ng) h = header[g0 + tid];
+        rec[tid] = h;
+        if (tid == 0) span[0] = h.base;
+        if (tid == ng - 1) span[1] = h.base + prefix_sq(h.sizes, 8);   // end of the range's cells
+        __syncthreads();
+        const uint32_t c0 = span[0], nc = span[1] - span[0];
+        if (nc <= kRMapCells) {
+            // every cell of the lane's group gets its bucket
+            if (tid < ng) {
+                for (uint32_t k = 0; k < 8; ++k) {
+                    const uint32_t sb = nib(h.sizes, k);
+                    const uint32_t at = h.base - c0 + prefix_sq(h.sizes, k);
+                    for (uint32_t p = 0; p < sb * sb; ++p) owner[at + p] = (uint16_t)((tid << 3) | k);
+                }
+            }
+            __syncthreads();
+            for (uint32_t e0 = 0; e0 < nc; e0 += kVBlock * kRUnroll) {
+                Cell x[kRUnroll];
 #pragma unroll
-        for (uint32_t k = 0; k < kRCells; ++k) {
-            const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
-            x[k] = i < S ? slots[i] : Cell{0, 0, 0};
-        }
-        uint32_t j[kRCells];
-        Group h[kRCells];
+                for (uint32_t u = 0; u < kRUnroll; ++u) {
+                    const uint32_t e = e0 + u * kVBlock + tid;
+                    x[u] = e < nc && (uint64_t)c0 + e < S ? slots[(uint64_t)c0 + e] : Cell{0, 0, 0};
+                }
 #pragma unroll
-        for (uint32_t k = 0; k < kRCells; ++k) {
-            const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
-            j[k] = fastmod(mshash(A, x[k].key), magic, n);
-            h[k] = i < S ? header[j[k] >> 3] : Group{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < kRCells; ++k) {
-            const uint64_t i = base + threadIdx.x + (uint64_t)k * kVBlock;
-            const uint32_t b = j[k] & 7u;
-            const uint32_t s = nib(h[k].sizes, b);
-            const uint32_t t = s == 1 ? 0u : group_t(h[k], b);   // a one-key bucket's byte is a tag
-            if (s == 0 || t >= T) continue;
-            const uint32_t s2 = s * s;
-            const uint64_t own = (uint64_t)h[k].base + prefix_sq(h[k].sizes, b) + mshash(C[t], x[k].key) % s2;
-            if (own == i) acc = combine(op, acc, cell_value(x[k], V64));
+                for (uint32_t u = 0; u < kRUnroll; ++u) {
+                    const uint32_t e = e0 + u * kVBlock + tid;
+                    if (e >= nc || (uint64_t)c0 + e >= S) continue;
+                    const uint32_t o = owner[e];
+                    const Group& r = rec[o >> 3];
+                    const uint32_t k = o & 7u, sb = nib(r.sizes, k);
+                    const uint32_t t = sb == 1 ? 0u : group_t(r, k);   // a one-key bucket's byte is a tag
+                    if (t >= T) continue;
+                    const uint32_t local = c0 + e - (r.base + prefix_sq(r.sizes, k));
+                    if (fastmod(mshash(C[t], x[u].key), mag[sb], sb * sb) == local)
+                        acc = combine(op, acc, cell_value(x[u], V64));
+                }
+            }
+        } else if (tid < ng) {
+            // a range too large for the map: the lane walks its own group's buckets
+            for (uint32_t k = 0; k < 8; ++k) {
+                const uint32_t sb = nib(h.sizes, k);
+                const uint32_t t = sb == 1 ? 0u : group_t(h, k);
+                if (sb == 0 || t >= T) continue;
+                const uint32_t s2 = sb * sb;
+                const uint64_t start = (uint64_t)h.base + prefix_sq(h.sizes, k);
+                if (start + s2 > S) continue;
+                for (uint32_t l = 0; l < s2; ++l) {
+                    const Cell x = slots[start + l];
+                    if (mshash(C[t], x.key) % s2 == l) acc = combine(op, acc, cell_value(x, V64));
+                }
+            }
         }
     }
     const uint64_t r = block_fold(acc, op, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (tid == 0) partial[blockIdx.x] = r;
 }
 
 // second pass: one workgroup folds the partials (none for an empty map)
@@ -230,8 +265,8 @@ namespace fks {
 
 // workgroups of the reduction's first pass (each strides over the table beyond that)
 static uint32_t reduce_partials(const fks_map* map) {
-    const uint64_t per = (uint64_t)kVBlock * kRCells;
-    uint64_t np = (map->S + per - 1) / per;
+    const uint64_t G = (map->n + 7) / 8;
+    uint64_t np = (G + kVBlock - 1) / kVBlock;
     return (uint32_t)(np > kVGrid ? kVGrid : np);
 }
 
@@ -245,15 +280,14 @@ static int reduce_launch(const fks_map* map, uint32_t op, uint64_t* d_out, uint6
     if (G == 0) {
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, nullptr, 0u, op, ident, d_out);
     } else {
-        const uint32_t n32 = (uint32_t)map->n;
         if (v64)
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_cells<true>, np, kVBlock, 0, st, map->header, map->slots, map->S,
-                                         map->A, map->magic_n, n32, map->C, map->T, op, ident, partial));
+                      hipLaunchKernelGGL(k_reduce_ranges<true>, np, kVBlock, 0, st, map->header, map->slots, G,
+                                         map->S, map->C, map->T, op, ident, partial));
         else
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_cells<false>, np, kVBlock, 0, st, map->header, map->slots, map->S,
-                                         map->A, map->magic_n, n32, map->C, map->T, op, ident, partial));
+                      hipLaunchKernelGGL(k_reduce_ranges<false>, np, kVBlock, 0, st, map->header, map->slots, G,
+                                         map->S, map->C, map->T, op, ident, partial));
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, partial, np, op, ident, d_out);
     }
     const hipError_t e = hipGetLastError();
