@@ -11,6 +11,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "fks_oracle.c"), os.path.join(_HERE, "search_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same sources with their independent loops run by OpenMP on every host core
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OK, EINVAL, ENOMEM, EDUPKEY, EBUILD = 0, -1, -2, -3, -4
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDUPKEY: "EDUPKEY", EBUILD: "EBUILD"}
@@ -23,66 +25,91 @@ class OracleError(RuntimeError):
 
 
 def compile_oracle() -> str:
-    """Compile the C oracles into ``oracle/liboracle.so`` (gcc, plain -O2)."""
-    tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                           "-o", tmp] + _SRCS)
-    os.replace(tmp, _LIB)
+    """Compile the C oracles into ``oracle/liboracle.so`` (gcc, plain -O2, sequential) and
+    ``oracle/liboracle_omp.so`` (the same sources with -fopenmp)."""
+    for lib, extra in ((_LIB, ["-Wno-unknown-pragmas"]), (_LIB_OMP, ["-fopenmp"])):
+        tmp = lib + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", *extra, "-shared", "-fPIC",
+                               "-o", tmp] + _SRCS)
+        os.replace(tmp, lib)
     return _LIB
 
 
 def ensure_built() -> str:
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
+    newest = max(os.path.getmtime(f) for f in _SRCS)
+    if any(not os.path.exists(p) or os.path.getmtime(p) < newest for p in (_LIB, _LIB_OMP)):
         compile_oracle()
     return _LIB
 
 
 _lib = None
+_lib_omp = None
+
+
+def liboracle_omp():
+    """The OpenMP build: the same functions, their independent loops on every host core
+    (OMP_NUM_THREADS threads); its results are those of the sequential build."""
+    global _lib_omp
+    if _lib_omp is None:
+        ensure_built()
+        _lib_omp = _configure(ctypes.CDLL(_LIB_OMP))
+    return _lib_omp
+
+
+def threads(omp: bool) -> int:
+    """Host threads the oracle's loops run on."""
+    return int((liboracle_omp() if omp else liboracle()).oracle_threads())
 
 
 def liboracle():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(ensure_built())
-        u64, u32, vp, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
-        lib.oracle_splitmix.restype = u64
-        lib.oracle_splitmix.argtypes = [u64, u64]
-        lib.oracle_hash.restype = u32
-        lib.oracle_hash.argtypes = [u64, u64, u64, u64]
-        lib.oracle_level1_consts.restype = None
-        lib.oracle_level1_consts.argtypes = [u64, u32, vp]
-        lib.oracle_level2_consts.restype = None
-        lib.oracle_level2_consts.argtypes = [u64, u32, u32, vp]
-        lib.oracle_fingerprint.restype = u64
-        lib.oracle_fingerprint.argtypes = [vp, u64, u64]
-        lib.oracle_build_u64.restype = i32
-        lib.oracle_build_u64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
-        lib.oracle_build_u64_dedup.restype = i32
-        lib.oracle_build_u64_dedup.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
-        lib.oracle_build_bytes.restype = i32
-        lib.oracle_build_bytes.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
-        lib.oracle_lookup_u64.restype = i32
-        lib.oracle_lookup_u64.argtypes = [vp, vp, u64, vp, vp, u32]
-        lib.oracle_lookup_bytes.restype = i32
-        lib.oracle_lookup_bytes.argtypes = [vp, vp, vp, u64, vp, vp, u32]
-        lib.oracle_info.restype = None
-        lib.oracle_info.argtypes = [vp, vp]
-        lib.oracle_export.restype = None
-        lib.oracle_export.argtypes = [vp, vp, vp]
-        lib.oracle_free.restype = None
-        lib.oracle_free.argtypes = [vp]
-        lib.oracle_batch_seed.restype = u64
-        lib.oracle_batch_seed.argtypes = [u64, u64]
-        lib.oracle_build_u64_v64.restype = i32
-        lib.oracle_build_u64_v64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
-        lib.oracle_lookup_u64_v64.restype = i32
-        lib.oracle_lookup_u64_v64.argtypes = [vp, vp, u64, vp, vp, u64]
-        lib.oracle_search_build.restype = i32
-        lib.oracle_search_build.argtypes = [vp, vp, u64, u32, vp, vp]
-        lib.oracle_search_lookup.restype = i32
-        lib.oracle_search_lookup.argtypes = [vp, vp, u64, u32, vp, u64, vp, vp, u32]
-        _lib = lib
+        _lib = _configure(ctypes.CDLL(ensure_built()))
     return _lib
+
+
+def _configure(lib):
+    """Argument and result types of every exported function."""
+    u64, u32, vp, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    lib.oracle_splitmix.restype = u64
+    lib.oracle_splitmix.argtypes = [u64, u64]
+    lib.oracle_hash.restype = u32
+    lib.oracle_hash.argtypes = [u64, u64, u64, u64]
+    lib.oracle_level1_consts.restype = None
+    lib.oracle_level1_consts.argtypes = [u64, u32, vp]
+    lib.oracle_level2_consts.restype = None
+    lib.oracle_level2_consts.argtypes = [u64, u32, u32, vp]
+    lib.oracle_fingerprint.restype = u64
+    lib.oracle_fingerprint.argtypes = [vp, u64, u64]
+    lib.oracle_build_u64.restype = i32
+    lib.oracle_build_u64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+    lib.oracle_build_u64_dedup.restype = i32
+    lib.oracle_build_u64_dedup.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+    lib.oracle_build_bytes.restype = i32
+    lib.oracle_build_bytes.argtypes = [vp, vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+    lib.oracle_lookup_u64.restype = i32
+    lib.oracle_lookup_u64.argtypes = [vp, vp, u64, vp, vp, u32]
+    lib.oracle_lookup_bytes.restype = i32
+    lib.oracle_lookup_bytes.argtypes = [vp, vp, vp, u64, vp, vp, u32]
+    lib.oracle_info.restype = None
+    lib.oracle_info.argtypes = [vp, vp]
+    lib.oracle_export.restype = None
+    lib.oracle_export.argtypes = [vp, vp, vp]
+    lib.oracle_free.restype = None
+    lib.oracle_free.argtypes = [vp]
+    lib.oracle_batch_seed.restype = u64
+    lib.oracle_batch_seed.argtypes = [u64, u64]
+    lib.oracle_build_u64_v64.restype = i32
+    lib.oracle_build_u64_v64.argtypes = [vp, vp, u64, u64, u32, u32, u32, ctypes.POINTER(vp)]
+    lib.oracle_lookup_u64_v64.restype = i32
+    lib.oracle_lookup_u64_v64.argtypes = [vp, vp, u64, vp, vp, u64]
+    lib.oracle_search_build.restype = i32
+    lib.oracle_search_build.argtypes = [vp, vp, u64, u32, vp, vp]
+    lib.oracle_search_lookup.restype = i32
+    lib.oracle_search_lookup.argtypes = [vp, vp, u64, u32, vp, u64, vp, vp, u32]
+    lib.oracle_threads.restype = i32
+    lib.oracle_threads.argtypes = []
+    return lib
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -125,10 +152,11 @@ INFO_FIELDS = ("n", "S", "r", "T", "c", "kind", "beta", "a0", "a1", "a2",
 class OracleMap:
     """A map built by the C oracle; owns the C object."""
 
-    def __init__(self, handle: int):
+    def __init__(self, handle: int, lib=None):
+        self._lib = lib if lib is not None else liboracle()
         self._h = ctypes.c_void_p(handle)
         info = np.zeros(len(INFO_FIELDS), np.uint64)
-        liboracle().oracle_info(self._h, _ptr(info))
+        self._lib.oracle_info(self._h, _ptr(info))
         self.info = {k: int(v) for k, v in zip(INFO_FIELDS, info)}
         self.n, self.S, self.r = self.info["n"], self.info["S"], self.info["r"]
         self.kind = {0: "u64", 1: "bytes", 2: "u64v64"}[self.info["kind"]]
@@ -136,7 +164,7 @@ class OracleMap:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            liboracle().oracle_free(h)
+            self._lib.oracle_free(h)
             self._h = None
 
     def export(self):
@@ -144,14 +172,14 @@ class OracleMap:
         ng = (self.n + 7) // 8
         header = np.zeros(16 * ng, np.uint8)
         slots = np.zeros(16 * self.S, np.uint8)
-        liboracle().oracle_export(self._h, _ptr(header), _ptr(slots))
+        self._lib.oracle_export(self._h, _ptr(header), _ptr(slots))
         return header, slots
 
     def lookup(self, queries: np.ndarray, missing: int = 0xFFFFFFFF):
         q = np.ascontiguousarray(queries, np.uint64)
         vals = np.zeros(q.size, np.uint32)
         found = np.zeros(q.size, np.uint8)
-        rc = liboracle().oracle_lookup_u64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
+        rc = self._lib.oracle_lookup_u64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
         if rc:
             raise OracleError(rc)
         return vals, found
@@ -160,7 +188,7 @@ class OracleMap:
         q = np.ascontiguousarray(queries, np.uint64)
         vals = np.zeros(q.size, np.uint64)
         found = np.zeros(q.size, np.uint8)
-        rc = liboracle().oracle_lookup_u64_v64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
+        rc = self._lib.oracle_lookup_u64_v64(self._h, _ptr(q), q.size, _ptr(vals), _ptr(found), missing)
         if rc:
             raise OracleError(rc)
         return vals, found
@@ -173,7 +201,7 @@ class OracleMap:
         m = off.size - 1
         vals = np.zeros(m, np.uint32)
         found = np.zeros(m, np.uint8)
-        rc = liboracle().oracle_lookup_bytes(self._h, _ptr(off), _ptr(buf), m, _ptr(vals),
+        rc = self._lib.oracle_lookup_bytes(self._h, _ptr(off), _ptr(buf), m, _ptr(vals),
                                              _ptr(found), missing)
         if rc:
             raise OracleError(rc)
@@ -181,15 +209,17 @@ class OracleMap:
 
 
 def build_u64(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int = 64,
-              R: int = 16) -> OracleMap:
+              R: int = 16, omp: bool = False) -> OracleMap:
+    """With omp, the OpenMP build of the oracle builds (and later queries) the map."""
     k = np.ascontiguousarray(keys, np.uint64)
     v = np.ascontiguousarray(vals, np.uint32)
     assert k.size == v.size
+    lib = liboracle_omp() if omp else liboracle()
     h = ctypes.c_void_p()
-    rc = liboracle().oracle_build_u64(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
+    rc = lib.oracle_build_u64(_ptr(k), _ptr(v), k.size, sigma, c, T, R, ctypes.byref(h))
     if rc:
         raise OracleError(rc)
-    return OracleMap(h.value)
+    return OracleMap(h.value, lib)
 
 
 def build_u64_v64(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, T: int = 64,
@@ -219,7 +249,7 @@ def build_u64_dedup(keys: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4, 
 
 
 def build_bytes(offsets: np.ndarray, data: np.ndarray, vals: np.ndarray, sigma: int, c: int = 4,
-                T: int = 64, R: int = 16) -> OracleMap:
+                T: int = 64, R: int = 16, omp: bool = False) -> OracleMap:
     off = np.ascontiguousarray(offsets, np.int64)
     buf = np.ascontiguousarray(data, np.uint8)
     if buf.size == 0:
@@ -227,12 +257,12 @@ def build_bytes(offsets: np.ndarray, data: np.ndarray, vals: np.ndarray, sigma: 
     v = np.ascontiguousarray(vals, np.uint32)
     n = off.size - 1
     assert v.size == n
+    lib = liboracle_omp() if omp else liboracle()
     h = ctypes.c_void_p()
-    rc = liboracle().oracle_build_bytes(_ptr(off), _ptr(buf), _ptr(v), n, sigma, c, T, R,
-                                        ctypes.byref(h))
+    rc = lib.oracle_build_bytes(_ptr(off), _ptr(buf), _ptr(v), n, sigma, c, T, R, ctypes.byref(h))
     if rc:
         raise OracleError(rc)
-    return OracleMap(h.value)
+    return OracleMap(h.value, lib)
 
 
 def search_build(keys: np.ndarray, vals: np.ndarray, layout: int):

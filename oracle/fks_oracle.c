@@ -59,6 +59,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_GAMMA 0x9E3779B97F4A7C15ULL
 #define OR_STRIDE 772u          /* stream entries per level-one attempt */
@@ -191,10 +194,10 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
     /* shape = hist n hashes (rep n 1) -- bucket sizes, squared below */
     uint64_t* shape = calloc(n, sizeof(uint64_t));
     if (!g || !shape) { free(g); free(shape); return OR_ENOMEM; }
-    for (uint64_t i = 0; i < n; ++i) {
+    #pragma omp parallel for schedule(static)
+    for (uint64_t i = 0; i < n; ++i)
         g[i] = oracle_hash(c1[0], c1[1], c1[2], keyv[i]) % (uint32_t)n;
-        shape[g[i]] += 1;
-    }
+    for (uint64_t i = 0; i < n; ++i) shape[g[i]] += 1;
     for (uint64_t j = 0; j < n; ++j) {
         if (shape[j] > OR_SMAX) {
             free(g); free(shape);
@@ -230,10 +233,9 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
     /* level-two constants of this attempt, shared by all buckets */
     uint64_t* C = malloc(sizeof(uint64_t) * 3 * M->T);
     uint8_t* tvals = calloc(n, 1);
-    uint8_t* seen = malloc(OR_SMAX * OR_SMAX);
-    if (!C || !tvals || !seen) {
+    if (!C || !tvals) {
         free(g); free(shape); free(offsets); free(gstart); free(gfill); free(members);
-        free(C); free(tvals); free(seen);
+        free(C); free(tvals);
         return OR_ENOMEM;
     }
     for (uint32_t t = 0; t < M->T; ++t) oracle_level2_consts(M->sigma, r, t, C + 3 * t);
@@ -242,10 +244,12 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
        have no collision (hist over s^2 cells, no count above one) */
     int exhausted = 0, dup = 0;
     uint64_t trials = 0;
+    #pragma omp parallel for schedule(dynamic, 4096) reduction(|: exhausted, dup) reduction(+: trials)
     for (uint64_t j = 0; j < n; ++j) {
         uint64_t s = shape[j];
         if (s <= 1) { tvals[j] = 0; continue; }
         uint32_t m2 = (uint32_t)(s * s);
+        uint8_t seen[OR_SMAX * OR_SMAX];
         int found = 0;
         for (uint32_t t = 0; t < M->T; ++t) {
             memset(seen, 0, m2);
@@ -273,7 +277,7 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
     }
     if (exhausted) {
         free(g); free(shape); free(offsets); free(gstart); free(gfill); free(members);
-        free(C); free(tvals); free(seen);
+        free(C); free(tvals);
         if (dup) return OR_EDUPKEY;
         M->attempts_rejected_exhausted++;
         return 1;
@@ -286,9 +290,10 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
     uint8_t* occupied = calloc(S ? S : 1, 1);
     if (!header || !slots || !occupied) {
         free(g); free(shape); free(offsets); free(gstart); free(gfill); free(members);
-        free(C); free(tvals); free(seen); free(header); free(slots); free(occupied);
+        free(C); free(tvals); free(header); free(slots); free(occupied);
         return OR_ENOMEM;
     }
+    #pragma omp parallel for schedule(static)
     for (uint64_t gi = 0; gi < ngroups; ++gi) {
         uint32_t sizes = 0;
         for (uint32_t k = 0; k < 8; ++k) {
@@ -302,7 +307,8 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
         or_put_u32(header + 16 * gi, (uint32_t)offsets[8 * gi]);
         or_put_u32(header + 16 * gi + 4, sizes);
     }
-    /* every key at h k */
+    /* every key at h k (each key has its own cell: the table is collision free) */
+    #pragma omp parallel for schedule(static)
     for (uint64_t i = 0; i < n; ++i) {
         uint64_t j = g[i];
         uint64_t s = shape[j];
@@ -317,6 +323,7 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
         occupied[p] = 1;
     }
     /* empty cells copy the lowest occupied cell of the same bucket */
+    #pragma omp parallel for schedule(static)
     for (uint64_t j = 0; j < n; ++j) {
         if (shape[j] == 0) continue;
         uint64_t lo = offsets[j], hi = offsets[j + 1], first = hi;
@@ -334,7 +341,7 @@ static int or_attempt(oracle_map* M, const uint64_t* keyv, const uint32_t* vals,
     M->slots = slots;
     M->level2_trials = trials;
     free(g); free(shape); free(offsets); free(gstart); free(gfill); free(members);
-    free(tvals); free(seen); free(occupied);
+    free(tvals); free(occupied);
     return OR_OK;
 }
 
@@ -591,6 +598,7 @@ int oracle_lookup_u64(const oracle_map* M, const uint64_t* q, uint64_t m,
                       uint32_t* vals, uint8_t* found, uint32_t missing)
 {
     if (M->kind != OR_KIND_U64) return OR_EINVAL;
+    #pragma omp parallel for schedule(static)
     for (uint64_t i = 0; i < m; ++i) {
         int64_t p = or_probe(M, q[i]);
         int hit = p >= 0 && or_get_u64(M->slots + 16 * (uint64_t)p) == q[i];
@@ -604,6 +612,7 @@ int oracle_lookup_u64_v64(const oracle_map* M, const uint64_t* q, uint64_t m,
                           uint64_t* vals, uint8_t* found, uint64_t missing)
 {
     if (M->kind != OR_KIND_U64V64) return OR_EINVAL;
+    #pragma omp parallel for schedule(static)
     for (uint64_t i = 0; i < m; ++i) {
         int64_t p = or_probe(M, q[i]);
         const uint8_t* cell = M->slots + 16 * (uint64_t)(p >= 0 ? p : 0);
@@ -618,6 +627,7 @@ int oracle_lookup_bytes(const oracle_map* M, const int64_t* qoff, const uint8_t*
                         uint64_t m, uint32_t* vals, uint8_t* found, uint32_t missing)
 {
     if (M->kind != OR_KIND_BYTES) return OR_EINVAL;
+    #pragma omp parallel for schedule(static)
     for (uint64_t i = 0; i < m; ++i) {
         uint64_t len = (uint64_t)(qoff[i + 1] - qoff[i]);
         const uint8_t* s = qbytes + qoff[i];
@@ -642,6 +652,20 @@ int oracle_lookup_bytes(const oracle_map* M, const int64_t* qoff, const uint8_t*
 }
 
 /* ---- introspection ------------------------------------------------------ */
+
+/* Threads the loops marked "omp parallel for" run on: this file built with OpenMP
+   (the all-cores leg of the CPU baseline) runs those independent loops -- one key,
+   one bucket, one group or one query per iteration, each writing only its own
+   entries -- on every host core; the plain build runs every loop in order.  Both
+   give the same bytes. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* info[0..]: n, S, r, T, c, kind, beta, a0, a1, a2, rejected(size),
    rejected(space), rejected(exhausted), level-two trials */

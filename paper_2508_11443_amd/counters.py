@@ -18,6 +18,14 @@ into a markdown table of per-kernel dispatch durations and resources with
 and any counter run (for instance the SQ instruction counters) into a table with
 
     python -m paper_2508_11443_amd.counters table COUNTER_COLLECTION.csv
+
+What one counted read request of the L2 moves is measured on the random-read probe: the
+GPU program ``python -m paper_2508_11443_amd.counters run-probe`` (run under rocprofv3
+--pmc) reads 16, 32, 64 and 128 contiguous bytes at uniform random places, and
+
+    python -m paper_2508_11443_amd.counters probe-table RUN1.csv [RUN2.csv ...]
+
+tabulates the counters per dispatch and per read.
 """
 from __future__ import annotations
 
@@ -134,7 +142,64 @@ def counter_table(csv_path: str) -> str:
     return "\n".join(lines)
 
 
+PROBE_READS = 1 << 27
+PROBE_WIDTHS = (16, 32, 64, 128)
+
+
+def run_probe():
+    """GPU program for counter runs over the random-read probe: one 1 GiB device copy (known
+    bytes, for scaling), then fks_probe_random_reads at every width: 2^27 reads from a 2 GiB
+    buffer, each width launched twice (warm-up and timed) with its own kernel instance."""
+    import torch
+    from . import fks
+    dev = torch.device("cuda:0")
+    src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    for w in PROBE_WIDTHS:
+        ms = fks.fks_probe_random_reads(2 << 30, PROBE_READS, w)
+        print(f"probe width {w} B: {PROBE_READS / (ms * 1e-3) / 1e9:.2f} G reads/s", flush=True)
+
+
+def probe_table(*csv_paths) -> str:
+    """Per probe width: every counter of the given --pmc runs per dispatch and per read, and
+    the same counters for the 1 GiB copy per 128-byte line it streams."""
+    per = {}
+    copy = {}
+    for path in csv_paths:
+        for r in _rows(path):
+            name, v = r["Kernel_Name"], float(r["Counter_Value"])
+            if "k_probe_random" in name:
+                vec = int(_short(name).split("<")[1].rstrip(">"))
+                per.setdefault(16 * vec, {}).setdefault(r["Counter_Name"], []).append(v)
+            elif "copy" in name.lower():
+                copy.setdefault(r["Counter_Name"], []).append(v)
+    names = sorted({c for e in per.values() for c in e})
+    lines = ["| reads of | " + " | ".join(f"{c} / dispatch" for c in names) + " | " +
+             " | ".join(f"{c} / read" for c in names) + " |", "|---|" + "---|" * (2 * len(names))]
+    for w in sorted(per):
+        avg = {c: statistics.median(v) for c, v in per[w].items()}
+        lines.append(f"| {w} B | " + " | ".join(f"{avg.get(c, float('nan')):.4g}" for c in names) + " | " +
+                     " | ".join(f"{avg.get(c, float('nan')) / PROBE_READS:.3f}" for c in names) + " |")
+    if copy:
+        lines_gib = GIB // 128
+        big = {c: max(v) for c, v in copy.items()}
+        lines.append(f"| 1 GiB copy (per 128-B line read) | " + " | ".join(f"{big.get(c, float('nan')):.4g}"
+                                                                           for c in names) + " | " +
+                     " | ".join(f"{big.get(c, float('nan')) / lines_gib:.3f}" for c in names) + " |")
+    return "\n".join(lines)
+
+
 def main(argv):
+    if len(argv) >= 2 and argv[1] == "run-probe":
+        run_probe()
+        return
+    if len(argv) >= 3 and argv[1] == "probe-table":
+        print(probe_table(*argv[2:]))
+        return
     if len(argv) >= 3 and argv[1] == "trace":
         print(trace_table(argv[2]))
         return

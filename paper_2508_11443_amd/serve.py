@@ -109,7 +109,7 @@ def run(wl: Workload, budget_bytes: int, rate_scale: float = 1.0, graphs: bool =
     srv.destroy()
     sub, done, kind, status = sub[first_rid:], done[first_rid:], kind[first_rid:], status[first_rid:]
     lat = done - sub
-    res = {"requests": len(wl.requests), "status_ok": bool((status == 0).all()),
+    res = {"requests": len(wl.requests), "status_ok": bool((status == 0).all()), "status": status.tolist(),
            "span_ms": float(done.max() - sub.min()), "stats": stats}
     for k, name in ((0, "build"), (1, "lookup")):
         sel = kind == k
@@ -117,6 +117,20 @@ def run(wl: Workload, budget_bytes: int, rate_scale: float = 1.0, graphs: bool =
             res[f"{name}_p50_ms"] = float(np.percentile(lat[sel], 50))
             res[f"{name}_p99_ms"] = float(np.percentile(lat[sel], 99))
             res[f"{name}_count"] = int(sel.sum())
+            # p99 over the first and the last quarter of the stream (in submission order): a
+            # queue that grows over the stream shows as a later p99 far above the earlier one
+            ls = lat[sel]
+            q = max(1, ls.size // 4)
+            res[f"{name}_p99_first_quarter_ms"] = float(np.percentile(ls[:q], 99))
+            res[f"{name}_p99_last_quarter_ms"] = float(np.percentile(ls[-q:], 99))
+    # the slowest requests: what they were and when they arrived (ms after the first)
+    worst = np.argsort(lat)[::-1][:5]
+    sizes = [r["size"] for r in wl.requests]
+    res["slowest"] = [{"kind": "build" if kind[i] == 0 else "lookup", "size": int(sizes[i]),
+                       "latency_ms": round(float(lat[i]), 3), "submitted_at_ms": round(float(sub[i] - sub[0]), 3)}
+                      for i in worst.tolist()]
+    res["failed"] = int((status != 0).sum())
+    res["failed_lookups"] = int(((status != 0) & (kind == 1)).sum())
     nq = sum(p[2].numel() for p in wl.plan if p[0] == "lookup")
     nk = sum(wl.maps[p[1]][3] for p in wl.plan if p[0] == "build")
     res["queries"] = int(nq)
@@ -126,12 +140,27 @@ def run(wl: Workload, budget_bytes: int, rate_scale: float = 1.0, graphs: bool =
     return res, outs
 
 
-def check(wl: Workload, outs):
-    """Every lookup's outputs against the exact expected answers."""
+def check(wl: Workload, outs, status=None):
+    """Every lookup's outputs against the exact expected answers.  With `status` (one entry
+    per request, as the server reported it), lookups the server refused -- their map was
+    evicted to make room -- are left out; every answered one must be exact."""
     import torch
     ok = True
-    for p, o in zip(wl.plan, outs):
+    for i, (p, o) in enumerate(zip(wl.plan, outs)):
         if p[0] == "lookup":
+            if status is not None and status[i] != 0:
+                continue
             v, f = o
             ok &= bool(torch.equal(f, p[3])) and bool(torch.equal(v, p[4]))
     return ok
+
+
+def stable(res, growth: float = 1.5, slack_ms: float = 1.0, span_slack: float = 1.2) -> bool:
+    """Whether an open-loop replay kept up with its arrivals: the lookups' p99 over the last
+    quarter of the stream stays within `growth` times (plus `slack_ms`) the p99 over its
+    first quarter, and the replay finished within `span_slack` times the arrival span."""
+    if "lookup_p99_last_quarter_ms" not in res or res["offered_rate_per_s"] is None:
+        return False
+    arrival_span_ms = res["requests"] / res["offered_rate_per_s"] * 1e3
+    return (res["lookup_p99_last_quarter_ms"] <= growth * res["lookup_p99_first_quarter_ms"] + slack_ms
+            and res["span_ms"] <= span_slack * arrival_span_ms + 5.0)

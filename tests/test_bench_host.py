@@ -31,3 +31,21 @@ def test_no_gpu_no_number():
     assert r.returncode != 0
     assert "needs a GPU" in r.stderr
     assert '"value"' not in r.stdout
+
+
+def test_cpu_legs_report_threads_and_host():
+    """Both CPU legs time the oracle on a power-of-two sample and name the threads they used
+    and the host's CPU."""
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2508_11443_amd import workloads
+    keys = workloads.unique_u64(1 << 12, 5)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    q, _ = workloads.u64_queries(keys, keys.size, 0.5, 6)
+    for omp in (False, True):
+        r = bench.cpu_leg(keys, vals, q, keys.size, 0.01, omp)
+        assert r["kind"] == "oracle" and r["value"] > 0 and r["nproc"] >= 1
+        assert r["cores"] == (1 if not omp else r["cores"]) and r["cores"] >= 1
+        assert str(keys.size) in r["sample"]
