@@ -32,7 +32,7 @@ constexpr int kBlock = 256;
 // control words of one attempt (device), read back through Readback
 struct Ctrl {
     uint64_t S;
-    uint32_t oversize, bad_input, exhausted, dup, max_t, pad;   // same layout as Readback
+    uint32_t oversize, bad_input, exhausted, dup, max_t, stalled;   // same layout as Readback
 };
 static_assert(sizeof(Ctrl) == sizeof(Readback), "read back as one block");
 // the final pass reads its two reject words from &oversize
@@ -59,7 +59,7 @@ __global__ void k_split_u64(const uint64_t* __restrict__ v, uint64_t n, uint32_t
 __global__ void k_zero_ctrl(Ctrl* c) {
     if (threadIdx.x == 0) {
         c->S = 0;
-        c->oversize = c->bad_input = c->exhausted = c->dup = c->max_t = c->pad = 0;
+        c->oversize = c->bad_input = c->exhausted = c->dup = c->max_t = c->stalled = 0;
     }
 }
 
@@ -220,6 +220,9 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     a.sizes = (uint32_t*)(base + o_sizes);
     a.S_dev = &ctrl->S;
     a.oversize = &ctrl->oversize;
+    a.stalled = &ctrl->stalled;
+    // the direct form runs the fused final pass: it sizes the partitions itself
+    a.fused = direct;
     const uint32_t* const reject = &ctrl->oversize;   // followed by bad_input
     if (direct) {
         cap = cells_guess(n, P.c);
@@ -276,6 +279,10 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             if ((rc = readback())) break;
             if (host->bad_input) {
                 rc = FKS_EINVAL;
+                break;
+            }
+            if (host->stalled) {
+                rc = hip_fail(hipErrorLaunchFailure);
                 break;
             }
             if (host->oversize) continue;

@@ -296,7 +296,7 @@ struct Readback {
     uint32_t exhausted;  // some bucket ran out of level-two trials
     uint32_t dup;        // an exhausted bucket holds two equal keys
     uint32_t max_t;
-    uint32_t pad;
+    uint32_t stalled;    // the fused final pass could not resolve a partition's first cell
 };
 
 }  // namespace fks

@@ -438,6 +438,29 @@ struct FinalLds {
     uint32_t nhard;
     uint32_t wsum[2][kPB / 64];
     uint32_t flags[3];   // exhausted, dup, max_t
+    uint64_t c0;         // fused form: the partition's first cell, from the look-back
+    uint32_t sqtot;      // the partition's sum of squared sizes
+    uint32_t ticket;     // fused form: the partition this workgroup works on
+    uint32_t over;       // fused form: a bucket above 15 keys
+};
+
+// look-back polls of one predecessor's word before the fused pass gives up (far beyond any
+// real wait: every predecessor publishes its sum without waiting on anything)
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// The fused final pass (single map, level-two search in partition order): each partition
+// takes a ticket, sizes its buckets itself, publishes its sum of squared sizes, and finds
+// its first cell by a look-back over its predecessors' published sums (a decoupled
+// look-back scan: the nearest predecessor that already published its inclusive prefix
+// ends it).  state holds one word per partition: value << 2 | 1 (the partition's own sum)
+// or value << 2 | 2 (the inclusive prefix); zero means not yet published.
+struct FuseArgs {
+    uint64_t* state;      // Q words, zero before the launch
+    uint32_t* ticket;     // zero before the launch
+    uint64_t* S_out;      // the table's S, written by the last partition
+    uint32_t* oversize;   // set when some bucket holds more than 15 keys
+    uint32_t* stalled;    // set when a look-back gave up
+    uint32_t Q;
 };
 
 // largest of a small value (below 16) over the wave's active lanes
@@ -483,7 +506,9 @@ __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T,
 // from its descriptor, cbase holds kSegParts+1 map-relative cell offsets per map,
 // and ctrl_flags points to four outcome words per map (a map whose word 0 is set was
 // rejected before this kernel and is skipped)
-template <bool AUX, bool STR, bool MULTI = false>
+// FUSED: the single map's final pass sizes its own partition and finds its first cell by
+// the look-back above (no separate size pass and scan; grid = Q)
+template <bool AUX, bool STR, bool MULTI = false, bool FUSED = false>
 __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                   const uint32_t* __restrict__ aux, int aux_is_pos, uint64_t n,
                                                   Triple A, uint64_t magic, const uint64_t* __restrict__ offQ,
@@ -495,11 +520,23 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                                                   const uint8_t* __restrict__ given_t,
                                                   const WideSeg* __restrict__ segs = nullptr,
                                                   const uint32_t* __restrict__ reject = nullptr,
-                                                  uint64_t cap = ~0ull) {
+                                                  uint64_t cap = ~0ull, FuseArgs fa = FuseArgs{}) {
+    static_assert(!(MULTI && FUSED), "the fused pass builds one map");
     __shared__ FinalLds<AUX> L;
     extern __shared__ Triple Cdyn[];   // the T level-two triples
     Triple* const LC = Cdyn;
-    const uint32_t q = blockIdx.x, tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
+    // an attempt already rejected by the size pass (a bucket above 15 keys) or by bad
+    // string offsets is skipped (both flags are set before this kernel starts)
+    if (reject && (reject[0] | reject[1])) return;   // the whole block
+    uint32_t q = blockIdx.x;
+    if (FUSED) {
+        // partitions go in ticket order: every partition a look-back below waits for was
+        // taken by a workgroup that is already running
+        if (tid == 0) L.ticket = atomicAdd(fa.ticket, 1u);
+        __syncthreads();
+        q = L.ticket;
+    }
     uint32_t qh = q;   // the partition's place among its map's partitions
     uint64_t cq = q;   // its entry in cbase
     if (MULTI) {
@@ -517,16 +554,20 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         ctrl_flags += 4 * mseg + 1;
         cq = (uint64_t)mseg * (kSegParts + 1) + qh;
     }
-    // an attempt already rejected by the size pass (a bucket above 15 keys) or by bad
-    // string offsets is skipped; so is a partition whose cells would end beyond the cells
-    // allocated (the attempt then runs this pass again into an exact allocation)
-    if (reject && (reject[0] | reject[1])) return;   // the whole block
     const uint64_t k0 = offQ[q], k1 = offQ[q + 1];
     const uint32_t nq = (uint32_t)(k1 - k0);
-    const uint64_t c0 = cbase[cq];
-    const uint32_t Sq = (uint32_t)(cbase[cq + 1] - c0);
-    if (c0 + Sq > cap) return;   // the whole block
-    const bool fast = nq <= kFinalKeyCap && Sq <= kFinalCellCap;
+    const bool keys_fit = nq <= kFinalKeyCap;
+    // a partition whose cells would end beyond the cells allocated is skipped (the attempt
+    // then runs this pass again into an exact allocation); the fused form learns its cells
+    // below
+    uint64_t c0 = 0;
+    uint32_t Sq = 0;
+    if (!FUSED) {
+        c0 = cbase[cq];
+        Sq = (uint32_t)(cbase[cq + 1] - c0);
+        if (c0 + Sq > cap) return;   // the whole block
+    }
+    bool fast = FUSED ? keys_fit : keys_fit && Sq <= kFinalCellCap;
     // the partition's records go in flight first; the set-up below overlaps their latency
     constexpr uint32_t KPT = kFinalKeyCap / kPB;
     static_assert(kFinalKeyCap % kPB == 0, "whole records per thread");
@@ -544,10 +585,13 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         }
     }
     for (uint32_t t = tid; t < T; t += kPB) LC[t] = Cg[t];
-    for (uint32_t g = tid; g < kGroupsPerPart; g += kPB)
-        L.words[g] = (uint64_t)qh * kGroupsPerPart + g < G ? sizes[(uint64_t)q * kGroupsPerPart + g] : 0u;
+    if (!FUSED) {
+        for (uint32_t g = tid; g < kGroupsPerPart; g += kPB)
+            L.words[g] = (uint64_t)qh * kGroupsPerPart + g < G ? sizes[(uint64_t)q * kGroupsPerPart + g] : 0u;
+    }
     if (tid < 3) L.flags[tid] = 0;
-    if (fast) {
+    if (FUSED && tid == 0) L.over = 0;
+    if (FUSED || fast) {
         for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.cnt2[g] = 0;
         for (uint32_t b = tid; b < kPartBuckets; b += kPB) L.tb[b] = 0;
         for (uint32_t w = tid; w < kFinalCellCap / 32; w += kPB) L.occ[w] = 0;
@@ -556,6 +600,44 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         if (tid == 0) L.nhard = 0;
     }
     __syncthreads();
+    uint32_t lbk[KPT], rk[KPT], c0k[KPT];
+    // stage the partition's records (when they fit); ranks come from an LDS histogram of
+    // the 4-bit bucket sizes, which the fused form also takes as the partition's sizes
+    auto stage = [&]() {
+        bool over = false;
+#pragma unroll
+        for (uint32_t k = 0; k < KPT; ++k) {
+            const uint32_t i = tid + k * kPB;
+            if (i < nq) {
+                L.key[i] = xk[k];
+                L.val[i] = vk[k];
+                if (AUX) L.aux[i] = ak[k];
+                const uint32_t lb = bucket_of(A, magic, (uint32_t)n, xk[k]) & (kPartBuckets - 1);
+                lbk[k] = lb;
+                const uint32_t sh = 4 * (lb & 7u);
+                rk[k] = (atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u;
+                over |= rk[k] == 15u;   // this key is the bucket's sixteenth
+            }
+        }
+        return over;
+    };
+    if (FUSED) {
+        bool over = false;
+        if (keys_fit) {
+            over = stage();
+        } else {
+            // too many keys to stage: their sizes from one pass over them
+            for (uint32_t i = tid; i < nq; i += kPB) {
+                const uint32_t lb = bucket_of(A, magic, (uint32_t)n, keys[k0 + i]) & (kPartBuckets - 1);
+                const uint32_t sh = 4 * (lb & 7u);
+                over |= ((atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u) == 15u;
+            }
+        }
+        if (over) atomicOr(&L.over, 1u);
+        __syncthreads();
+        for (uint32_t g = tid; g < kGroupsPerPart; g += kPB) L.words[g] = L.cnt2[g];
+        __syncthreads();
+    }
     // group statistics: where each group's keys and cells start inside the partition
     {
         uint32_t c = 0, s2 = 0;
@@ -592,23 +674,67 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             L.gks[tid] = pc + ic - c;
             L.gbase[tid] = ps + is - s2;
         }
+        if (tid == kGroupsPerPart - 1) L.sqtot = ps + is;
     }
-    if (fast) {
-        // stage the partition's keys; ranks come from a second LDS histogram
-        uint32_t lbk[KPT], rk[KPT], c0k[KPT];
-#pragma unroll
-        for (uint32_t k = 0; k < KPT; ++k) {
-            const uint32_t i = tid + k * kPB;
-            if (i < nq) {
-                L.key[i] = xk[k];
-                L.val[i] = vk[k];
-                if (AUX) L.aux[i] = ak[k];
-                const uint32_t lb = bucket_of(A, magic, (uint32_t)n, xk[k]) & (kPartBuckets - 1);
-                lbk[k] = lb;
-                const uint32_t sh = 4 * (lb & 7u);
-                rk[k] = (atomicAdd(&L.cnt2[lb >> 3], 1u << sh) >> sh) & 15u;
+    // fused form: the partition's first cell, from the predecessors' published sums back to
+    // the nearest published inclusive prefix (64 per round: lane l reads partition
+    // end - 1 - l); then this partition's inclusive prefix is published.  Called by the
+    // whole workgroup just before the cells are written, when the predecessors' sums, which
+    // each publishes as soon as it has sized its buckets, are there to read.
+    auto lookback = [&]() {
+        if (tid < 64) {
+            const uint32_t lane = tid;
+            uint64_t excl = 0;
+            int64_t end = (int64_t)q;
+            for (;;) {
+                const int64_t idx = end - 1 - (int64_t)lane;
+                uint64_t v = 2;   // before the first partition: an inclusive prefix of 0
+                if (idx >= 0) {
+                    uint32_t spins = 0;
+                    for (;;) {
+                        v = __hip_atomic_load(&fa.state[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (v & 3u) break;
+                        if (++spins > kSpinLimit) {
+                            atomicOr(fa.stalled, 1u);
+                            v = 2;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                const uint64_t incl = __ballot((v & 3u) == 2u);
+                uint64_t take = v >> 2;
+                const bool last = incl != 0;
+                if (last && lane > (uint32_t)(__ffsll((long long)incl) - 1)) take = 0;
+                for (int d = 32; d >= 1; d >>= 1) take += __shfl_xor(take, d, 64);
+                excl += take;
+                if (last) break;
+                end -= 64;
+            }
+            if (lane == 0) {
+                L.c0 = excl;
+                __hip_atomic_store(&fa.state[q], ((excl + Sq) << 2) | 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (q + 1 == fa.Q) *fa.S_out = excl + Sq;
             }
         }
+        __syncthreads();
+        c0 = L.c0;
+    };
+    if (FUSED) {
+        __syncthreads();
+        Sq = L.sqtot;
+        // publish this partition's sum at once: the look-backs of later partitions read it
+        if (tid == 0)
+            __hip_atomic_store(&fa.state[q], ((uint64_t)Sq << 2) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (L.over) {
+            lookback();
+            if (tid == 0) atomicOr(fa.oversize, 1u);
+            return;   // the whole block: the attempt is rejected
+        }
+        fast = keys_fit && Sq <= kFinalCellCap;
+    }
+    if (fast) {
+        if (!FUSED) (void)stage();
         __syncthreads();
         // group by bucket.  A lone key owns its bucket's single cell.  Every key of a
         // larger bucket tries trial 0 at once: the second key to claim a cell marks
@@ -624,10 +750,10 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 c0k[k] = off;
                 if (s == 1) {
                     L.smap[off] = (uint16_t)i;
-                    L.tb[lb] = (uint8_t)key_tag(LC[0], xk[k]);   // trial 0; the byte holds the key's tag
+                    L.tb[lb] = (uint8_t)key_tag(LC[0], L.key[i]);   // trial 0; the byte holds the key's tag
                 } else {
                     if (!given_t) {
-                        const uint32_t cell = off + fastmod(mshash(LC[0], xk[k]), L.mag[s], s * s);
+                        const uint32_t cell = off + fastmod(mshash(LC[0], L.key[i]), L.mag[s], s * s);
                         c0k[k] = cell;
                         const uint32_t bit = 1u << (cell & 31u), bb = 1u << (lb & 31u);
                         if ((atomicOr(&L.occ[cell >> 5], bit) & bit) && !(atomicOr(&L.fl[lb >> 5], bb) & bb))
@@ -700,13 +826,17 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 if (sb >= 2) {
                     const uint32_t t = L.tb[lb];
                     const uint32_t cell = (t || given_t) ? L.gbase[g] + prefix_sq(w, kk) +
-                                                               fastmod(mshash(LC[t], xk[k]), L.mag[sb], sb * sb)
+                                                               fastmod(mshash(LC[t], L.key[i]), L.mag[sb], sb * sb)
                                                          : c0k[k];
                     L.smap[cell] = (uint16_t)i;
                 }
             }
         }
         __syncthreads();
+        if (FUSED) {
+            lookback();
+            if (c0 + Sq > cap) return;   // the whole block
+        }
         // write-out: indices first (a marked cell resolves to the bucket's lowest
         // occupied cell; every bucket holds a key), then the records
         constexpr uint32_t CPT = kFinalCellCap / kPB;
@@ -741,6 +871,10 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         // rare: the partition does not fit the LDS staging; every bucket gathers its
         // own keys from HBM (a scan of the partition), searches and writes its cells
         __syncthreads();
+        if (FUSED) {
+            lookback();
+            if (c0 + Sq > cap) return;   // the whole block
+        }
         for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
             const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
             const uint32_t s = nib(w, kk);
@@ -992,6 +1126,11 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         o.aux = a.a1;
         o.aux_is_pos = aux ? 0 : 1;
     }
+    if (a.fused) {
+        // the fused final pass sizes the partitions and finds their cell bases itself
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? FKS_OK : hip_fail(e);
+    }
     FKS_TIMED("fks_part_sizes", st,
               hipLaunchKernelGGL(k_psizes, P.Q, kPB, 0, st, o.keys, n, a.A, a.magic, a.offQ, a.sizes, a.G, a.sqQ,
                                  a.oversize));
@@ -1006,9 +1145,37 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     return e == hipSuccess ? FKS_OK : hip_fail(e);
 }
 
+template <bool AUX, bool STR>
+static void launch_fused(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
+                         uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint32_t* reject,
+                         uint64_t cap, hipStream_t st) {
+    const uint32_t Q = o.plan.Q;
+    // the look-back words (in the cell-base scratch) and the ticket (in the partition-sum
+    // scratch) start at zero
+    hipLaunchKernelGGL(k_zero_words, (2 * Q + 255) / 256, 256, 0, st, reinterpret_cast<uint32_t*>(a.cbase),
+                       (uint64_t)2 * Q);
+    hipLaunchKernelGGL(k_zero_words, 1, 64, 0, st, a.sqQ, (uint64_t)1);
+    const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q};
+    FKS_TIMED("fks_part_final", st,
+              hipLaunchKernelGGL((k_pfinal<AUX, STR, false, true>), Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                                 AUX ? o.aux : nullptr, AUX ? o.aux_is_pos : 1, a.n, a.A, a.magic, a.offQ, a.cbase,
+                                 a.sizes, a.G, C, T, header, slots, flags, ctx_off, ctx_bytes, nullptr, nullptr,
+                                 reject, cap, fa));
+}
+
 int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
                 const uint32_t* reject, uint64_t cap, hipStream_t st) {
+    if (a.fused && !given_t) {
+        if (a.aux && a.str)
+            launch_fused<true, true>(a, o, C, T, header, slots, flags, ctx_off, ctx_bytes, reject, cap, st);
+        else if (a.aux)
+            launch_fused<true, false>(a, o, C, T, header, slots, flags, nullptr, nullptr, reject, cap, st);
+        else
+            launch_fused<false, false>(a, o, C, T, header, slots, flags, nullptr, nullptr, reject, cap, st);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? FKS_OK : hip_fail(e);
+    }
     if (a.aux && a.str)
         FKS_TIMED("fks_part_final", st,
                   hipLaunchKernelGGL((k_pfinal<true, true>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,

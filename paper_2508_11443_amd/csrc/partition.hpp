@@ -67,6 +67,8 @@ struct PartArgs {
     uint32_t* sizes;            // G size words (the headers' second word)
     uint64_t* S_dev;            // total cells
     uint32_t* oversize;         // a bucket above 15 keys
+    uint32_t* stalled;          // fused final pass: a look-back gave up
+    bool fused;                 // the final pass sizes the partitions itself (no size pass and scan)
 };
 
 struct PartOut {
