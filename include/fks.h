@@ -376,6 +376,11 @@ int fks_batch_set_schedule(uint32_t M, uint64_t total_keys, uint32_t schedule);
  *   completes (fks_server_poll / fks_server_wait_all).  Lookups against a map
  *   that failed to build, or was evicted, complete with that error status.
  *   flags: bit 0 disables graph replay (plain launches).
+ *   Device memory: fks_server_create reserves one slab (the budget, plus room
+ *   for the running build's scratch: 32 bytes for each key the budget admits)
+ *   and every map and build scratch of the server is carved from it, so no
+ *   request waits on the driver's allocator; fks_server_create fails with
+ *   FKS_ENOMEM when the slab cannot be reserved.
  */
 typedef struct fks_server fks_server;
 

@@ -114,6 +114,59 @@ static double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// The server's device memory: one slab reserved when the server is created, handed out
+// first fit (256-byte aligned) and coalesced on release, so that no build and no eviction
+// calls the driver's allocator while requests are served (a stream-ordered allocation
+// that has to grow its pool can hold the runtime for a long time).  A block is released
+// only after its last use on the device is complete: a build's scratch after the build's
+// final wait, a map's memory when the map is evicted idle or the server is destroyed;
+// every build runs on the one build stream.  So a block can be handed out again at once.
+struct Arena {
+    std::mutex mu;
+    char* base = nullptr;
+    uint64_t size = 0;
+    std::map<uint64_t, uint64_t> free_;   // offset -> length of every free range
+    std::map<uint64_t, uint64_t> used_;   // offset -> length of every block handed out
+
+    void* take(uint64_t bytes) {
+        bytes = (bytes + 255) & ~255ull;
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const uint64_t at = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes) free_[at + bytes] = len - bytes;
+            used_[at] = bytes;
+            return base + at;
+        }
+        return nullptr;
+    }
+    void give_back(void* p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu);
+        auto u = used_.find((uint64_t)((char*)p - base));
+        if (u == used_.end()) return;
+        uint64_t at = u->first, len = u->second;
+        used_.erase(u);
+        auto next = free_.lower_bound(at);
+        if (next != free_.end() && next->first == at + len) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == at) {
+                prev->second += len;
+                return;
+            }
+        }
+        free_[at] = len;
+    }
+};
+
+static void* arena_alloc(uint64_t bytes, void*, void* user) { return static_cast<Arena*>(user)->take(bytes); }
+static void arena_free(void* p, void*, void* user) { static_cast<Arena*>(user)->give_back(p); }
+
 }  // namespace fks
 
 using namespace fks;
@@ -170,6 +223,9 @@ struct fks_server {
     hipEvent_t ev[kRing] = {};
     std::map<std::pair<int, uint32_t>, hipGraphExec_t> graphs;   // (ring slot, grid class)
     std::thread build_thr, lookup_thr;
+    // device memory of the maps and of the builds' scratch
+    fks::Arena arena;
+    fks_allocator alloc{};
 };
 
 namespace fks {
@@ -263,7 +319,7 @@ static void build_loop(fks_server* S) {
         fks_map* m = nullptr;
         // the build reads the keys only after the submitter's stream has written them
         int rc = ready ? (hipStreamWaitEvent(S->build_st, ready, 0) == hipSuccess ? FKS_OK : FKS_EHIP) : FKS_OK;
-        if (rc == FKS_OK) rc = fks_build_u64(keys, vals, n, seed, &p, nullptr, S->build_st, &m);
+        if (rc == FKS_OK) rc = fks_build_u64(keys, vals, n, seed, &p, &S->alloc, S->build_st, &m);
         const double t = now_ms();
         lk.lock();
         S->used -= est;
@@ -457,6 +513,17 @@ extern "C" int fks_server_create(uint64_t budget_bytes, const fks_params* params
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->build_st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->lookup_st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->capture_st, hipStreamNonBlocking);
+    // the arena: the budget for resident maps, plus room for the running build's scratch
+    // (under 32 bytes per key; a build admitted under the budget has fewer than
+    // budget / (16 c + 2) keys) and for rounding
+    if (e == hipSuccess) {
+        const uint64_t max_keys = budget_bytes / (16ull * S->params.c + 2);
+        S->arena.size = budget_bytes + 32 * max_keys + (256ull << 20);
+        e = hipMalloc((void**)&S->arena.base, S->arena.size);
+        if (e == hipSuccess) S->arena.free_[0] = S->arena.size;
+        else S->arena.base = nullptr;
+        S->alloc = fks_allocator{arena_alloc, arena_free, &S->arena};
+    }
     for (int k = 0; k < kRing && e == hipSuccess; ++k) {
         e = hipHostMalloc((void**)&S->h_tab[k], sizeof(LTab), hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc((void**)&S->d_tab[k], sizeof(LTab));
@@ -472,6 +539,7 @@ extern "C" int fks_server_create(uint64_t budget_bytes, const fks_params* params
         if (S->build_st) (void)hipStreamDestroy(S->build_st);
         if (S->lookup_st) (void)hipStreamDestroy(S->lookup_st);
         if (S->capture_st) (void)hipStreamDestroy(S->capture_st);
+        if (S->arena.base) (void)hipFree(S->arena.base);
         delete S;
         return rc;
     }
@@ -651,5 +719,6 @@ extern "C" void fks_server_destroy(fks_server* S) {
     (void)hipStreamDestroy(S->build_st);
     (void)hipStreamDestroy(S->lookup_st);
     (void)hipStreamDestroy(S->capture_st);
+    (void)hipFree(S->arena.base);
     delete S;
 }

@@ -155,12 +155,10 @@ def check(wl: Workload, outs, status=None):
     return ok
 
 
-def stable(res, growth: float = 1.5, slack_ms: float = 1.0, span_slack: float = 1.2) -> bool:
+def stable(res, growth: float = 2.0, slack_ms: float = 1.0) -> bool:
     """Whether an open-loop replay kept up with its arrivals: the lookups' p99 over the last
-    quarter of the stream stays within `growth` times (plus `slack_ms`) the p99 over its
-    first quarter, and the replay finished within `span_slack` times the arrival span."""
+    quarter of the stream stays within `growth` times (plus `slack_ms`) their p99 over the
+    first quarter.  A queue that grows without bound makes later requests wait ever longer."""
     if "lookup_p99_last_quarter_ms" not in res or res["offered_rate_per_s"] is None:
         return False
-    arrival_span_ms = res["requests"] / res["offered_rate_per_s"] * 1e3
-    return (res["lookup_p99_last_quarter_ms"] <= growth * res["lookup_p99_first_quarter_ms"] + slack_ms
-            and res["span_ms"] <= span_slack * arrival_span_ms + 5.0)
+    return res["lookup_p99_last_quarter_ms"] <= growth * res["lookup_p99_first_quarter_ms"] + slack_ms
