@@ -32,7 +32,7 @@ constexpr int kBlock = 256;
 // control words of one attempt (device), read back through Readback
 struct Ctrl {
     uint64_t S;
-    uint32_t oversize, bad_input, exhausted, dup, max_t, stalled;   // same layout as Readback
+    uint32_t oversize, bad_input, exhausted, dup, max_t, stalled, overflow, pad;   // same layout as Readback
 };
 static_assert(sizeof(Ctrl) == sizeof(Readback), "read back as one block");
 // the final pass reads its two reject words from &oversize
@@ -59,7 +59,7 @@ __global__ void k_split_u64(const uint64_t* __restrict__ v, uint64_t n, uint32_t
 __global__ void k_zero_ctrl(Ctrl* c) {
     if (threadIdx.x == 0) {
         c->S = 0;
-        c->oversize = c->bad_input = c->exhausted = c->dup = c->max_t = c->stalled = 0;
+        c->oversize = c->bad_input = c->exhausted = c->dup = c->max_t = c->stalled = c->overflow = c->pad = 0;
     }
 }
 
@@ -186,10 +186,17 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         total += (bytes_ + 255) & ~(size_t)255;
         return at;
     };
-    const size_t o_k1 = plan.passes >= 2 ? carve(8 * n) : 0, o_v1 = plan.passes >= 2 ? carve(4 * n) : 0;
-    const size_t o_a1 = plan.passes >= 2 && carry ? carve(4 * n) : 0;
-    const size_t o_k2 = plan.passes >= 1 ? carve(8 * n) : 0, o_v2 = plan.passes >= 1 ? carve(4 * n) : 0;
-    const size_t o_a2 = plan.passes >= 1 && carry ? carve(4 * n) : 0;
+    // two passes in the direct form reserve their runs on cursors: the records then sit in
+    // fixed-capacity regions (binsA of them after the first pass, Q after the second)
+    const bool cursor = direct && plan.passes == 2;
+    const uint64_t r1 = cursor ? std::max<uint64_t>(n, plan.cap1 * plan.binsA) : n;
+    const uint64_t r2 = cursor ? std::max<uint64_t>(n, plan.capQ * Q) : n;
+    const size_t o_k1 = plan.passes >= 2 ? carve(8 * r1) : 0, o_v1 = plan.passes >= 2 ? carve(4 * r1) : 0;
+    const size_t o_a1 = plan.passes >= 2 && carry ? carve(4 * r1) : 0;
+    const size_t o_k2 = plan.passes >= 1 ? carve(8 * r2) : 0, o_v2 = plan.passes >= 1 ? carve(4 * r2) : 0;
+    const size_t o_a2 = plan.passes >= 1 && carry ? carve(4 * r2) : 0;
+    const size_t o_cur1 = cursor ? carve(8 * (size_t)plan.binsA) : 0, o_cur2 = cursor ? carve(8 * (size_t)Q) : 0;
+    const size_t o_begA = cursor ? carve(8 * (size_t)plan.binsA) : 0, o_begQ = cursor ? carve(8 * (size_t)Q) : 0;
     const size_t o_cnt = carve(4 * plan.matrix), o_off = carve(4 * plan.matrix);
     const size_t o_tsum = carve(4 * part_scan_tiles(plan)), o_tpre = carve(8 * (part_scan_tiles(plan) + 1));
     const size_t o_offA = carve(8 * 257), o_offQ = carve(8 * ((size_t)Q + 1)), o_sqQ = carve(4 * (size_t)Q);
@@ -218,11 +225,19 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     a.sqQ = (uint32_t*)(base + o_sqQ);
     a.cbase = (uint64_t*)(base + o_cbase);
     a.sizes = (uint32_t*)(base + o_sizes);
+    if (cursor) {
+        a.cur1 = (unsigned long long*)(base + o_cur1);
+        a.cur2 = (unsigned long long*)(base + o_cur2);
+        a.begA = (uint64_t*)(base + o_begA);
+        a.begQ = (uint64_t*)(base + o_begQ);
+    }
+    a.overflow = &ctrl->overflow;
     a.S_dev = &ctrl->S;
     a.oversize = &ctrl->oversize;
     a.stalled = &ctrl->stalled;
     // the direct form runs the fused final pass: it sizes the partitions itself
     a.fused = direct;
+    a.cursor = cursor;
     const uint32_t* const reject = &ctrl->oversize;   // followed by bad_input
     if (direct) {
         cap = cells_guess(n, P.c);
@@ -284,6 +299,13 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             if (host->stalled) {
                 rc = hip_fail(hipErrorLaunchFailure);
                 break;
+            }
+            if (host->overflow) {
+                // a region of the cursor passes overflowed (keys far from uniform over the
+                // partitions): the same attempt again with counted passes
+                a.cursor = false;
+                --r;
+                continue;
             }
             if (host->oversize) continue;
             const uint64_t S = host->S;

@@ -297,6 +297,8 @@ struct Readback {
     uint32_t dup;        // an exhausted bucket holds two equal keys
     uint32_t max_t;
     uint32_t stalled;    // the fused final pass could not resolve a partition's first cell
+    uint32_t overflow;   // a fixed-capacity region of the cursor passes overflowed
+    uint32_t pad;
 };
 
 }  // namespace fks

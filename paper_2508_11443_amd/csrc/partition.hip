@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "fks_internal.hpp"
 #include "partition.hpp"
@@ -57,14 +58,15 @@ __device__ __forceinline__ uint32_t bucket_of(const Triple& A, uint64_t magic, u
 // contiguous chunk of it and walks the chunk in tiles, so that counting and
 // scattering see the keys in the same order.
 __device__ __forceinline__ void worker_range(const uint64_t* ranges, uint64_t n, uint32_t W, uint64_t& a,
-                                             uint64_t& b, const WideSeg* segs = nullptr) {
+                                             uint64_t& b, const WideSeg* segs = nullptr,
+                                             const uint64_t* ranges_hi = nullptr) {
     uint64_t lo = 0, hi = n;
     if (segs) {
         lo = segs[blockIdx.y].in_lo;
         hi = segs[blockIdx.y].in_hi;
     } else if (ranges) {
         lo = ranges[blockIdx.y];
-        hi = ranges[blockIdx.y + 1];
+        hi = ranges_hi ? ranges_hi[blockIdx.y] : ranges[blockIdx.y + 1];
     }
     const uint64_t chunk = (hi - lo + W - 1) / W;
     a = min(hi, lo + (uint64_t)blockIdx.x * chunk);
@@ -129,7 +131,14 @@ __device__ __forceinline__ uint32_t block_exscan256(uint32_t v, uint32_t* wsum) 
 // bin's run is written to consecutive addresses from the worker's scanned
 // offset (no device atomics; the output order is a function of the input).
 // BT threads per block (at least one per bin), ITEMS records per thread per tile
-template <bool AUX, uint32_t ITEMS, uint32_t BT = kPB>
+// CURSOR: instead of offsets from a count matrix, every tile reserves each bin's run with
+// one atomic add on the bin's cursor (bins are fixed-capacity regions: bin i of segment s
+// owns [(s * (mask + 1) + i) * cap, ... + cap)); records that would land beyond their
+// region are dropped and *overflow is raised, so the attempt can be redone with counts.
+// Segment s reads [ranges[s], ranges_hi[s]).  The order of records inside a bin then
+// depends on timing, which the final pass does not see: its table depends only on which
+// records each partition holds.
+template <bool AUX, uint32_t ITEMS, uint32_t BT = kPB, bool CURSOR = false>
 __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ aux, uint64_t n, Triple A,
@@ -137,22 +146,27 @@ __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ ke
                                                     uint32_t shift, uint32_t mask, const uint32_t* __restrict__ off,
                                                     uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                     uint32_t* __restrict__ aux_out,
-                                                    const WideSeg* __restrict__ segs = nullptr) {
+                                                    const WideSeg* __restrict__ segs = nullptr,
+                                                    unsigned long long* __restrict__ cursor = nullptr,
+                                                    const uint64_t* __restrict__ ranges_hi = nullptr,
+                                                    uint64_t cap = 0, uint32_t* __restrict__ overflow = nullptr) {
     __shared__ uint64_t skey[(BT * ITEMS)];
     __shared__ uint32_t sval[(BT * ITEMS)];
     __shared__ uint32_t saux[AUX ? (BT * ITEMS) : 1];
     __shared__ uint32_t run[kBins], tcnt[kBins], toff[kBins];
     __shared__ uint32_t wsum[BT / 64];
     static_assert(BT >= kBins && BT % 64 == 0, "one bin per thread");
+    __shared__ uint64_t lim[CURSOR ? kBins : 1];
     uint64_t a, b;
-    worker_range(ranges, n, W, a, b, segs);
+    worker_range(ranges, n, W, a, b, segs, ranges_hi);
     if (segs) {
         A = segs[blockIdx.y].A;
         magic = segs[blockIdx.y].magic;
         n = segs[blockIdx.y].n;
     }
     const uint32_t tid = threadIdx.x;
-    if (tid < kBins) run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
+    if (!CURSOR && tid < kBins) run[tid] = off[((uint64_t)blockIdx.y * kBins + tid) * W + blockIdx.x];
+    if (CURSOR && tid < kBins) lim[tid] = ((uint64_t)blockIdx.y * (mask + 1) + tid + 1) * cap;
     // a tile's records are loaded into registers one tile ahead: the loads of
     // tile i+1 are in flight while tile i is written out
     uint64_t x[ITEMS];
@@ -181,6 +195,13 @@ __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ ke
             }
         }
         __syncthreads();
+        if (CURSOR && tid <= mask && tcnt[tid]) {
+            // this tile's run of bin tid: reserved now, written after the tile is sorted
+            const unsigned long long at =
+                atomicAdd(&cursor[(uint64_t)blockIdx.y * (mask + 1) + tid], (unsigned long long)tcnt[tid]);
+            run[tid] = (uint32_t)at;
+            if (at + tcnt[tid] > lim[tid]) atomicOr(overflow, 1u);
+        }
         {
             const uint32_t e = block_exscan256(tid < kBins ? tcnt[tid] : 0u, wsum);
             if (tid < kBins) toff[tid] = e;
@@ -204,13 +225,31 @@ __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ ke
             // and a staged byte per record measured the same
             const uint32_t bb = ((bucket_of(A, magic, (uint32_t)n, skey[e]) >> kPartBits) >> shift) & mask;
             const uint64_t dest = (uint64_t)run[bb] + (e - toff[bb]);
+            if (CURSOR && dest >= lim[bb]) continue;   // beyond the bin's region: dropped, overflow raised
             keys_out[dest] = skey[e];
             vals_out[dest] = sval[e];
             if (AUX) aux_out[dest] = saux[e];
         }
         __syncthreads();
-        if (tid < kBins) run[tid] += tcnt[tid];
+        if (!CURSOR && tid < kBins) run[tid] += tcnt[tid];
     }
+}
+
+// cursor of fixed-capacity region i starts at i * cap (begin[i] keeps that start)
+__global__ void k_init_cursors(unsigned long long* __restrict__ cursor, uint64_t* __restrict__ begin, uint64_t count,
+                               uint64_t cap) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        cursor[i] = i * cap;
+        if (begin) begin[i] = i * cap;
+    }
+}
+
+// a cursor that ran past its region's end is brought back to it (the overflow flag is up)
+__global__ void k_clamp_cursors(unsigned long long* __restrict__ cursor, uint64_t count, uint64_t cap) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        if (cursor[i] > (i + 1) * cap) cursor[i] = (i + 1) * cap;
 }
 
 // ---- exclusive scan of a u32 array across blocks (values sum below 2^32) --------------------
@@ -461,6 +500,7 @@ struct FuseArgs {
     uint32_t* oversize;   // set when some bucket holds more than 15 keys
     uint32_t* stalled;    // set when a look-back gave up
     uint32_t Q;
+    const uint64_t* qend; // partition q's records are [offQ[q], qend[q])
 };
 
 // largest of a small value (below 16) over the wave's active lanes
@@ -554,7 +594,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         ctrl_flags += 4 * mseg + 1;
         cq = (uint64_t)mseg * (kSegParts + 1) + qh;
     }
-    const uint64_t k0 = offQ[q], k1 = offQ[q + 1];
+    const uint64_t k0 = offQ[q], k1 = FUSED ? fa.qend[q] : offQ[q + 1];
     const uint32_t nq = (uint32_t)(k1 - k0);
     const bool keys_fit = nq <= kFinalKeyCap;
     // a partition whose cells would end beyond the cells allocated is skipped (the attempt
@@ -998,6 +1038,16 @@ PartPlan part_plan(uint64_t n) {
         P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
         P.bitsB = P.shiftA;
         P.W2 = clampu((n / P.binsA + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
+        // regions of the cursor form: a first-level bin covers 2^shiftA partitions of 1024
+        // buckets and a partition 1024 buckets; with n keys in n buckets the keys of B buckets
+        // number B on average with a standard deviation of about sqrt(B), and the regions hold
+        // 12 deviations more (an overflow only sends the attempt back to the counted passes)
+        auto region = [](uint64_t B) {
+            const uint64_t sd = (uint64_t)std::ceil(std::sqrt((double)B));
+            return (B + 12 * sd + 64 + 255) & ~(uint64_t)255;
+        };
+        P.cap1 = region((uint64_t)kPartBuckets << P.shiftA);
+        P.capQ = region(kPartBuckets);
     } else {
         P.passes = 3;
         P.shiftA = bits - 8;
@@ -1037,6 +1087,19 @@ static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin,
                                  shift, mask, a.off, kout, vout, aout));
 }
 
+template <bool AUX>
+static void scatter_cursor(const PartArgs& a, const uint64_t* kin, const uint32_t* vin, const uint32_t* ain,
+                           const uint64_t* ranges, const uint64_t* ranges_hi, dim3 grid, uint32_t W, uint32_t shift,
+                           uint32_t mask, uint64_t* kout, uint32_t* vout, uint32_t* aout, unsigned long long* cursor,
+                           uint64_t cap, hipStream_t st) {
+    FKS_TIMED("fks_part_scatter", st,
+              hipLaunchKernelGGL((k_dscatter<AUX, AUX ? kPScatterItemsAux : kPScatterItems, kPScatterThreads, true>),
+                                 grid, kPScatterThreads, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W, shift,
+                                 mask, nullptr, kout, vout, aout, nullptr, cursor, ranges_hi, cap, a.overflow));
+}
+
+static unsigned grid_for_count(uint64_t count) { return (unsigned)std::min<uint64_t>((count + 255) / 256, 4096); }
+
 // Runs the partition passes of one attempt; stream-ordered outputs: offQ, the
 // records in partition order (o.keys/vals/aux), the size words, the partition
 // sums of squares, their scan (cbase) and the total S (*S_dev).
@@ -1049,6 +1112,8 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     o.vals = a.vals;
     o.aux = a.aux_in;
     o.aux_is_pos = a.aux_in ? 0 : 1;
+    o.qbeg = a.offQ;
+    o.qend = a.offQ + 1;
     auto count = [&](const uint64_t* kin, const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift,
                      uint32_t mask) {
         FKS_TIMED("fks_part_count", st,
@@ -1069,6 +1134,33 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         o.vals = a.v2;
         o.aux = a.a2;
         o.aux_is_pos = aux ? 0 : 1;
+    } else if (P.passes == 2 && a.cursor) {
+        // first-level bins, then partitions, each reserved run by run on the bin's cursor
+        hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.binsA), 256, 0, st, a.cur1, a.begA, (uint64_t)P.binsA,
+                           P.cap1);
+        hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.Q), 256, 0, st, a.cur2, a.begQ, (uint64_t)P.Q, P.capQ);
+        if (aux)
+            scatter_cursor<true>(a, a.keys, a.vals, a.aux_in, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255,
+                                 a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
+        else
+            scatter_cursor<false>(a, a.keys, a.vals, nullptr, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255,
+                                  a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
+        hipLaunchKernelGGL(k_clamp_cursors, grid_for_count(P.binsA), 256, 0, st, a.cur1, (uint64_t)P.binsA, P.cap1);
+        const uint32_t maskB = (1u << P.bitsB) - 1;
+        const uint64_t* hi1 = reinterpret_cast<const uint64_t*>(a.cur1);
+        if (aux)
+            scatter_cursor<true>(a, a.k1, a.v1, a.a1, a.begA, hi1, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2, a.v2,
+                                 a.a2, a.cur2, P.capQ, st);
+        else
+            scatter_cursor<false>(a, a.k1, a.v1, nullptr, a.begA, hi1, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2,
+                                  a.v2, a.a2, a.cur2, P.capQ, st);
+        hipLaunchKernelGGL(k_clamp_cursors, grid_for_count(P.Q), 256, 0, st, a.cur2, (uint64_t)P.Q, P.capQ);
+        o.keys = a.k2;
+        o.vals = a.v2;
+        o.aux = a.a2;
+        o.aux_is_pos = aux ? 0 : 1;
+        o.qbeg = a.begQ;
+        o.qend = reinterpret_cast<const uint64_t*>(a.cur2);
     } else if (P.passes == 2) {
         count(a.keys, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255);
         scan_matrix(a, (uint64_t)kBins * P.W1, st);
@@ -1155,10 +1247,10 @@ static void launch_fused(const PartArgs& a, const PartOut& o, const Triple* C, u
     hipLaunchKernelGGL(k_zero_words, (2 * Q + 255) / 256, 256, 0, st, reinterpret_cast<uint32_t*>(a.cbase),
                        (uint64_t)2 * Q);
     hipLaunchKernelGGL(k_zero_words, 1, 64, 0, st, a.sqQ, (uint64_t)1);
-    const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q};
+    const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q, o.qend};
     FKS_TIMED("fks_part_final", st,
               hipLaunchKernelGGL((k_pfinal<AUX, STR, false, true>), Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
-                                 AUX ? o.aux : nullptr, AUX ? o.aux_is_pos : 1, a.n, a.A, a.magic, a.offQ, a.cbase,
+                                 AUX ? o.aux : nullptr, AUX ? o.aux_is_pos : 1, a.n, a.A, a.magic, o.qbeg, a.cbase,
                                  a.sizes, a.G, C, T, header, slots, flags, ctx_off, ctx_bytes, nullptr, nullptr,
                                  reject, cap, fa));
 }

@@ -39,6 +39,8 @@ struct PartPlan {
     uint32_t bitsC;    // three passes: third-level bin = q & (2^bitsC - 1)
     uint32_t W1, W2, W3;   // workers of the first pass / per bin of the second and third passes
     uint64_t matrix;   // entries of the largest count matrix
+    // two passes with cursors: capacity of a first-level bin's region and of a partition's
+    uint64_t cap1, capQ;
 };
 
 // Inputs, scratch and outputs of one attempt (device pointers).
@@ -69,6 +71,14 @@ struct PartArgs {
     uint32_t* oversize;         // a bucket above 15 keys
     uint32_t* stalled;          // fused final pass: a look-back gave up
     bool fused;                 // the final pass sizes the partitions itself (no size pass and scan)
+    // two passes without count passes: each tile reserves its runs on per-bin cursors in
+    // fixed-capacity regions (k1/v1/a1 hold binsA * cap1 records, k2/v2/a2 Q * capQ)
+    bool cursor;
+    unsigned long long* cur1;   // binsA first-level cursors
+    unsigned long long* cur2;   // Q partition cursors: each partition's end
+    uint64_t* begA;             // binsA region starts
+    uint64_t* begQ;             // Q partition starts
+    uint32_t* overflow;         // a region overflowed: the attempt is redone with counts
 };
 
 struct PartOut {
@@ -77,6 +87,8 @@ struct PartOut {
     const uint32_t* vals;
     const uint32_t* aux;
     int aux_is_pos;
+    const uint64_t* qbeg;       // partition q's records are [qbeg[q], qend[q])
+    const uint64_t* qend;
 };
 
 // Exclusive prefix sum of N u32 counts whose total is below 2^32 (three launches):

@@ -188,6 +188,37 @@ def test_bench_size_bit_exact():
     torch.cuda.empty_cache()
 
 
+def test_crowded_partition_takes_the_counted_passes():
+    """With 2^18 < n <= 2^26 keys the build reserves each partition's records in a region of
+    fixed capacity (about 1.5x the 1024 keys a partition holds on average).  Here over 2000
+    keys hash (under attempt 0's level-one constants) into the first partition's 1024
+    buckets: its region overflows and the attempt is redone with counted passes.  The table
+    must still equal the oracle's byte for byte."""
+    from oracle import rounds, spec
+    n, seed = 300000, 0xC20D
+    announce(f"gpu single u64: crowded first partition, n={n} seed={seed}")
+    a0, a1, b, _ = spec.level1_consts(seed, 0)
+    rng = np.random.default_rng(99)
+    crowd = np.zeros(0, np.uint64)
+    while crowd.size < 2100:
+        cand = rng.integers(0, 1 << 64, size=1 << 22, dtype=np.uint64)
+        crowd = np.unique(np.concatenate([crowd, cand[rounds.hash_vec(a0, a1, b, cand) % n < 1024]]))
+    crowd = crowd[:2100]
+    rest = workloads.unique_u64(n, 7, dense_fraction=0.0)
+    rest = rest[~np.isin(rest, crowd)][:n - crowd.size]
+    keys = np.concatenate([crowd, rest])
+    assert np.unique(keys).size == n
+    assert (rounds.hash_vec(a0, a1, b, keys) % n < 1024).sum() > 2000
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.build_u64(keys, vals, seed)
+    assert ref.r == 0
+    m = gpu_build(keys, vals, seed)
+    assert_same_table(m, ref)
+    q, expect, src = workloads.u64_queries(keys, 1 << 16, 0.5, 5, return_index=True)
+    v, f = gpu_lookup(m, q)
+    assert (f == expect).all() and (v[expect == 1] == src[expect == 1].astype(np.uint32)).all()
+
+
 @pytest.mark.parametrize("n", [(1 << 26) + 1, (1 << 27) + 12345])
 def test_three_radix_passes_bit_exact(n):
     """More than 2^16 partitions of 1024 buckets: the partition index is grouped in three
