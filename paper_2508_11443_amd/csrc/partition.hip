@@ -59,14 +59,15 @@ __device__ __forceinline__ uint32_t bucket_of(const Triple& A, uint64_t magic, u
 // scattering see the keys in the same order.
 __device__ __forceinline__ void worker_range(const uint64_t* ranges, uint64_t n, uint32_t W, uint64_t& a,
                                              uint64_t& b, const WideSeg* segs = nullptr,
-                                             const uint64_t* ranges_hi = nullptr) {
+                                             const uint64_t* ranges_hi = nullptr, uint64_t hi_cap = 0) {
     uint64_t lo = 0, hi = n;
     if (segs) {
         lo = segs[blockIdx.y].in_lo;
         hi = segs[blockIdx.y].in_hi;
     } else if (ranges) {
         lo = ranges[blockIdx.y];
-        hi = ranges_hi ? ranges_hi[blockIdx.y] : ranges[blockIdx.y + 1];
+        // a cursor that ran past its region's end (overflow raised) stops at the end
+        hi = ranges_hi ? min(ranges_hi[blockIdx.y], lo + hi_cap) : ranges[blockIdx.y + 1];
     }
     const uint64_t chunk = (hi - lo + W - 1) / W;
     a = min(hi, lo + (uint64_t)blockIdx.x * chunk);
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ ke
                                                     const WideSeg* __restrict__ segs = nullptr,
                                                     unsigned long long* __restrict__ cursor = nullptr,
                                                     const uint64_t* __restrict__ ranges_hi = nullptr,
-                                                    uint64_t cap = 0, uint32_t* __restrict__ overflow = nullptr) {
+                                                    uint64_t cap = 0, uint32_t* __restrict__ overflow = nullptr,
+                                                    uint64_t in_cap = 0) {
     __shared__ uint64_t skey[(BT * ITEMS)];
     __shared__ uint32_t sval[(BT * ITEMS)];
     __shared__ uint32_t saux[AUX ? (BT * ITEMS) : 1];
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ ke
     static_assert(BT >= kBins && BT % 64 == 0, "one bin per thread");
     __shared__ uint64_t lim[CURSOR ? kBins : 1];
     uint64_t a, b;
-    worker_range(ranges, n, W, a, b, segs, ranges_hi);
+    worker_range(ranges, n, W, a, b, segs, ranges_hi, in_cap);
     if (segs) {
         A = segs[blockIdx.y].A;
         magic = segs[blockIdx.y].magic;
@@ -245,12 +247,6 @@ __global__ void k_init_cursors(unsigned long long* __restrict__ cursor, uint64_t
     }
 }
 
-// a cursor that ran past its region's end is brought back to it (the overflow flag is up)
-__global__ void k_clamp_cursors(unsigned long long* __restrict__ cursor, uint64_t count, uint64_t cap) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        if (cursor[i] > (i + 1) * cap) cursor[i] = (i + 1) * cap;
-}
 
 // ---- exclusive scan of a u32 array across blocks (values sum below 2^32) --------------------
 
@@ -500,7 +496,8 @@ struct FuseArgs {
     uint32_t* oversize;   // set when some bucket holds more than 15 keys
     uint32_t* stalled;    // set when a look-back gave up
     uint32_t Q;
-    const uint64_t* qend; // partition q's records are [offQ[q], qend[q])
+    const uint64_t* qend; // partition q's records are [offQ[q], min(qend[q], offQ[q] + qcap))
+    uint64_t qcap;        // 0: no cap
 };
 
 // largest of a small value (below 16) over the wave's active lanes
@@ -594,7 +591,8 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
         ctrl_flags += 4 * mseg + 1;
         cq = (uint64_t)mseg * (kSegParts + 1) + qh;
     }
-    const uint64_t k0 = offQ[q], k1 = FUSED ? fa.qend[q] : offQ[q + 1];
+    const uint64_t k0 = offQ[q];
+    const uint64_t k1 = !FUSED ? offQ[q + 1] : fa.qcap ? min(fa.qend[q], k0 + fa.qcap) : fa.qend[q];
     const uint32_t nq = (uint32_t)(k1 - k0);
     const bool keys_fit = nq <= kFinalKeyCap;
     // a partition whose cells would end beyond the cells allocated is skipped (the attempt
@@ -1089,13 +1087,14 @@ static void scatter(const PartArgs& a, const uint64_t* kin, const uint32_t* vin,
 
 template <bool AUX>
 static void scatter_cursor(const PartArgs& a, const uint64_t* kin, const uint32_t* vin, const uint32_t* ain,
-                           const uint64_t* ranges, const uint64_t* ranges_hi, dim3 grid, uint32_t W, uint32_t shift,
-                           uint32_t mask, uint64_t* kout, uint32_t* vout, uint32_t* aout, unsigned long long* cursor,
-                           uint64_t cap, hipStream_t st) {
+                           const uint64_t* ranges, const uint64_t* ranges_hi, uint64_t in_cap, dim3 grid, uint32_t W,
+                           uint32_t shift, uint32_t mask, uint64_t* kout, uint32_t* vout, uint32_t* aout,
+                           unsigned long long* cursor, uint64_t cap, hipStream_t st) {
     FKS_TIMED("fks_part_scatter", st,
               hipLaunchKernelGGL((k_dscatter<AUX, AUX ? kPScatterItemsAux : kPScatterItems, kPScatterThreads, true>),
                                  grid, kPScatterThreads, 0, st, kin, vin, ain, a.n, a.A, a.magic, ranges, W, shift,
-                                 mask, nullptr, kout, vout, aout, nullptr, cursor, ranges_hi, cap, a.overflow));
+                                 mask, nullptr, kout, vout, aout, nullptr, cursor, ranges_hi, cap, a.overflow,
+                                 in_cap));
 }
 
 static unsigned grid_for_count(uint64_t count) { return (unsigned)std::min<uint64_t>((count + 255) / 256, 4096); }
@@ -1114,6 +1113,7 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     o.aux_is_pos = a.aux_in ? 0 : 1;
     o.qbeg = a.offQ;
     o.qend = a.offQ + 1;
+    o.qcap = 0;   // no cap: the counted passes fill their ranges exactly
     auto count = [&](const uint64_t* kin, const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift,
                      uint32_t mask) {
         FKS_TIMED("fks_part_count", st,
@@ -1140,27 +1140,26 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
                            P.cap1);
         hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.Q), 256, 0, st, a.cur2, a.begQ, (uint64_t)P.Q, P.capQ);
         if (aux)
-            scatter_cursor<true>(a, a.keys, a.vals, a.aux_in, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255,
-                                 a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
+            scatter_cursor<true>(a, a.keys, a.vals, a.aux_in, nullptr, nullptr, 0, dim3(P.W1, 1), P.W1, P.shiftA,
+                                 255, a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
         else
-            scatter_cursor<false>(a, a.keys, a.vals, nullptr, nullptr, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255,
-                                  a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
-        hipLaunchKernelGGL(k_clamp_cursors, grid_for_count(P.binsA), 256, 0, st, a.cur1, (uint64_t)P.binsA, P.cap1);
+            scatter_cursor<false>(a, a.keys, a.vals, nullptr, nullptr, nullptr, 0, dim3(P.W1, 1), P.W1, P.shiftA,
+                                  255, a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
         const uint32_t maskB = (1u << P.bitsB) - 1;
         const uint64_t* hi1 = reinterpret_cast<const uint64_t*>(a.cur1);
         if (aux)
-            scatter_cursor<true>(a, a.k1, a.v1, a.a1, a.begA, hi1, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2, a.v2,
-                                 a.a2, a.cur2, P.capQ, st);
+            scatter_cursor<true>(a, a.k1, a.v1, a.a1, a.begA, hi1, P.cap1, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2,
+                                 a.v2, a.a2, a.cur2, P.capQ, st);
         else
-            scatter_cursor<false>(a, a.k1, a.v1, nullptr, a.begA, hi1, dim3(P.W2, P.binsA), P.W2, 0, maskB, a.k2,
-                                  a.v2, a.a2, a.cur2, P.capQ, st);
-        hipLaunchKernelGGL(k_clamp_cursors, grid_for_count(P.Q), 256, 0, st, a.cur2, (uint64_t)P.Q, P.capQ);
+            scatter_cursor<false>(a, a.k1, a.v1, nullptr, a.begA, hi1, P.cap1, dim3(P.W2, P.binsA), P.W2, 0, maskB,
+                                  a.k2, a.v2, a.a2, a.cur2, P.capQ, st);
         o.keys = a.k2;
         o.vals = a.v2;
         o.aux = a.a2;
         o.aux_is_pos = aux ? 0 : 1;
         o.qbeg = a.begQ;
         o.qend = reinterpret_cast<const uint64_t*>(a.cur2);
+        o.qcap = P.capQ;
     } else if (P.passes == 2) {
         count(a.keys, nullptr, dim3(P.W1, 1), P.W1, P.shiftA, 255);
         scan_matrix(a, (uint64_t)kBins * P.W1, st);
@@ -1247,7 +1246,7 @@ static void launch_fused(const PartArgs& a, const PartOut& o, const Triple* C, u
     hipLaunchKernelGGL(k_zero_words, (2 * Q + 255) / 256, 256, 0, st, reinterpret_cast<uint32_t*>(a.cbase),
                        (uint64_t)2 * Q);
     hipLaunchKernelGGL(k_zero_words, 1, 64, 0, st, a.sqQ, (uint64_t)1);
-    const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q, o.qend};
+    const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q, o.qend, o.qcap};
     FKS_TIMED("fks_part_final", st,
               hipLaunchKernelGGL((k_pfinal<AUX, STR, false, true>), Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
                                  AUX ? o.aux : nullptr, AUX ? o.aux_is_pos : 1, a.n, a.A, a.magic, o.qbeg, a.cbase,

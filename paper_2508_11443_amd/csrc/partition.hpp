@@ -87,8 +87,9 @@ struct PartOut {
     const uint32_t* vals;
     const uint32_t* aux;
     int aux_is_pos;
-    const uint64_t* qbeg;       // partition q's records are [qbeg[q], qend[q])
+    const uint64_t* qbeg;       // partition q's records are [qbeg[q], min(qend[q], qbeg[q] + qcap))
     const uint64_t* qend;
+    uint64_t qcap;              // 0: no cap (counted passes)
 };
 
 // Exclusive prefix sum of N u32 counts whose total is below 2^32 (three launches):
