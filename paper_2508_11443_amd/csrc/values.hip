@@ -103,12 +103,14 @@ __global__ __launch_bounds__(kVBlock) void k_reduce_ranges(const Group* __restri
                                                              const Cell* __restrict__ slots, uint64_t G, uint64_t S,
                                                              const Triple* __restrict__ Cg, uint32_t T, uint32_t op,
                                                              uint64_t ident, uint64_t* __restrict__ partial) {
-    __shared__ Triple C[kTMax];
+    extern __shared__ Triple C[];            // the map's T level-two triples
     __shared__ Group rec[kVBlock];
-    __shared__ uint16_t owner[kRMapCells];   // (group in the range << 3) | bucket
+    // (group in the range << 3) | bucket of each of the range's cells; at the end, the
+    // workgroup's fold (the map is no longer read then)
+    __shared__ __align__(16) uint16_t owner[kRMapCells];
     __shared__ uint64_t mag[16];
-    __shared__ uint64_t red[kVBlock];
     __shared__ uint32_t span[2];
+    static_assert(sizeof(owner) >= kVBlock * sizeof(uint64_t), "the fold fits the map");
     const uint32_t tid = threadIdx.x;
     for (uint32_t k = tid; k < T; k += kVBlock) C[k] = Cg[k];
     if (tid < 16) mag[tid] = tid ? fastmod_magic(tid * tid) : 0;
@@ -170,7 +172,8 @@ __global__ __launch_bounds__(kVBlock) void k_reduce_ranges(const Group* __restri
             }
         }
     }
-    const uint64_t r = block_fold(acc, op, red);
+    __syncthreads();   // the last range's map is no longer read
+    const uint64_t r = block_fold(acc, op, reinterpret_cast<uint64_t*>(owner));
     if (tid == 0) partial[blockIdx.x] = r;
 }
 
@@ -280,13 +283,14 @@ static int reduce_launch(const fks_map* map, uint32_t op, uint64_t* d_out, uint6
     if (G == 0) {
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, nullptr, 0u, op, ident, d_out);
     } else {
+        const size_t dyn = sizeof(Triple) * map->T;
         if (v64)
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_ranges<true>, np, kVBlock, 0, st, map->header, map->slots, G,
+                      hipLaunchKernelGGL(k_reduce_ranges<true>, np, kVBlock, dyn, st, map->header, map->slots, G,
                                          map->S, map->C, map->T, op, ident, partial));
         else
             FKS_TIMED("fks_reduce_values", st,
-                      hipLaunchKernelGGL(k_reduce_ranges<false>, np, kVBlock, 0, st, map->header, map->slots, G,
+                      hipLaunchKernelGGL(k_reduce_ranges<false>, np, kVBlock, dyn, st, map->header, map->slots, G,
                                          map->S, map->C, map->T, op, ident, partial));
         hipLaunchKernelGGL(k_reduce_final, 1, kVBlock, 0, st, partial, np, op, ident, d_out);
     }
