@@ -459,7 +459,6 @@ struct FinalLds {
     uint64_t key[kFinalKeyCap];
     uint32_t val[kFinalKeyCap];
     uint32_t aux[AUX ? kFinalKeyCap : 1];
-    uint16_t perm[kFinalKeyCap];
     uint16_t smap[kFinalCellCap];
     uint32_t words[kGroupsPerPart];
     uint32_t cnt2[kGroupsPerPart];
@@ -535,6 +534,12 @@ __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T,
     return T;
 }
 
+// waves per SIMD the final pass is compiled for (registers within 80, or 96 with an aux
+// word): the LDS of six workgroups (26.6 KB each), or five with an aux word (31.7 KB),
+// fits a CU
+template <bool AUX>
+constexpr unsigned kFinalWaves = AUX ? 5u : 6u;
+
 // AUX: an aux word travels with every key (a string key's index, or the high
 // half of a 64-bit value); STR: keys are string fingerprints, so equal keys
 // are told apart by their bytes
@@ -546,7 +551,7 @@ __device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T,
 // FUSED: the single map's final pass sizes its own partition and finds its first cell by
 // the look-back above (no separate size pass and scan; grid = Q)
 template <bool AUX, bool STR, bool MULTI = false, bool FUSED = false>
-__global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+__global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves<AUX>))) void k_pfinal(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                   const uint32_t* __restrict__ aux, int aux_is_pos, uint64_t n,
                                                   Triple A, uint64_t magic, const uint64_t* __restrict__ offQ,
                                                   const uint64_t* __restrict__ cbase, const uint32_t* __restrict__ sizes,
@@ -560,8 +565,6 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                                                   uint64_t cap = ~0ull, FuseArgs fa = FuseArgs{}) {
     static_assert(!(MULTI && FUSED), "the fused pass builds one map");
     __shared__ FinalLds<AUX> L;
-    extern __shared__ Triple Cdyn[];   // the T level-two triples
-    Triple* const LC = Cdyn;
     const uint32_t tid = threadIdx.x;
     // an attempt already rejected by the size pass (a bucket above 15 keys) or by bad
     // string offsets is skipped (both flags are set before this kernel starts)
@@ -622,7 +625,9 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
             }
         }
     }
-    for (uint32_t t = tid; t < T; t += kPB) LC[t] = Cg[t];
+    // the T level-two triples stay in global memory: a wave's search reads one triple at a
+    // time (one address per wave), and the placement's reads are cached
+    const Triple* const LC = Cg;
     if (!FUSED) {
         for (uint32_t g = tid; g < kGroupsPerPart; g += kPB)
             L.words[g] = (uint64_t)qh * kGroupsPerPart + g < G ? sizes[(uint64_t)q * kGroupsPerPart + g] : 0u;
@@ -639,17 +644,15 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
     }
     __syncthreads();
     uint32_t lbk[KPT], rk[KPT], c0k[KPT];
-    // stage the partition's records (when they fit); ranks come from an LDS histogram of
-    // the 4-bit bucket sizes, which the fused form also takes as the partition's sizes
+    // rank the partition's records (when they fit) in their buckets: ranks come from an LDS
+    // histogram of the 4-bit bucket sizes, which the fused form also takes as the
+    // partition's sizes.  The records stay in registers until they are grouped.
     auto stage = [&]() {
         bool over = false;
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
-                L.key[i] = xk[k];
-                L.val[i] = vk[k];
-                if (AUX) L.aux[i] = ak[k];
                 const uint32_t lb = bucket_of(A, magic, (uint32_t)n, xk[k]) & (kPartBuckets - 1);
                 lbk[k] = lb;
                 const uint32_t sh = 4 * (lb & 7u);
@@ -774,24 +777,31 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
     if (fast) {
         if (!FUSED) (void)stage();
         __syncthreads();
-        // group by bucket.  A lone key owns its bucket's single cell.  Every key of a
-        // larger bucket tries trial 0 at once: the second key to claim a cell marks
-        // its bucket as colliding, and only those buckets are searched below.
+        // group by bucket: each record goes to the LDS slot of its rank in its bucket, so a
+        // bucket's keys lie together (from here on a record is named by its slot).  A lone
+        // key owns its bucket's single cell.  Every key of a larger bucket tries trial 0 at
+        // once: the second key to claim a cell marks its bucket as colliding, and only those
+        // buckets are searched below.
+        const Triple c0t = LC[0];
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
                 const uint32_t lb = lbk[k], g = lb >> 3, kk = lb & 7u, w = L.words[g];
-                const uint32_t r = rk[k], s = nib(w, kk);
+                const uint32_t s = nib(w, kk);
                 const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
-                L.perm[L.gks[g] + prefix_cnt(w, kk) + r] = (uint16_t)i;
+                const uint32_t slot = L.gks[g] + prefix_cnt(w, kk) + rk[k];
+                rk[k] = slot;
+                L.key[slot] = xk[k];
+                L.val[slot] = vk[k];
+                if (AUX) L.aux[slot] = ak[k];
                 c0k[k] = off;
                 if (s == 1) {
-                    L.smap[off] = (uint16_t)i;
-                    L.tb[lb] = (uint8_t)key_tag(LC[0], L.key[i]);   // trial 0; the byte holds the key's tag
+                    L.smap[off] = (uint16_t)slot;
+                    L.tb[lb] = (uint8_t)key_tag(c0t, xk[k]);   // trial 0; the byte holds the key's tag
                 } else {
                     if (!given_t) {
-                        const uint32_t cell = off + fastmod(mshash(LC[0], L.key[i]), L.mag[s], s * s);
+                        const uint32_t cell = off + fastmod(mshash(c0t, xk[k]), L.mag[s], s * s);
                         c0k[k] = cell;
                         const uint32_t bit = 1u << (cell & 31u), bb = 1u << (lb & 31u);
                         if ((atomicOr(&L.occ[cell >> 5], bit) & bit) && !(atomicOr(&L.fl[lb >> 5], bb) & bb))
@@ -831,10 +841,10 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 const uint32_t smax = wave_max16(sb);
                 uint64_t kx[8];
 #pragma unroll
-                for (uint32_t i = 0; i < 8; ++i) kx[i] = i < sb ? L.key[L.perm[kst + i]] : 0;
+                for (uint32_t i = 0; i < 8; ++i) kx[i] = i < sb ? L.key[kst + i] : 0;
                 t = min_trial_small(LC, T, sb, kx, L.mag[sb], 1, smax);
             } else {
-                t = min_trial(LC, T, sb, [&](uint32_t i) { return L.key[L.perm[kst + i]]; }, 1);
+                t = min_trial(LC, T, sb, [&](uint32_t i) { return L.key[kst + i]; }, 1);
             }
             if (t < T) {
                 L.tb[b] = (uint8_t)t;
@@ -845,7 +855,7 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 bool dup = false;
                 for (uint32_t a2 = 0; a2 < sb; ++a2)
                     for (uint32_t b2 = a2 + 1; b2 < sb; ++b2) {
-                        const uint16_t ia = L.perm[kst + a2], ib = L.perm[kst + b2];
+                        const uint32_t ia = kst + a2, ib = kst + b2;
                         if (STR) dup |= same_string(ctx_off, ctx_bytes, L.aux[ia], L.aux[ib]);
                         else dup |= L.key[ia] == L.key[ib];
                     }
@@ -864,9 +874,9 @@ __global__ __launch_bounds__(kPB) void k_pfinal(const uint64_t* __restrict__ key
                 if (sb >= 2) {
                     const uint32_t t = L.tb[lb];
                     const uint32_t cell = (t || given_t) ? L.gbase[g] + prefix_sq(w, kk) +
-                                                               fastmod(mshash(LC[t], L.key[i]), L.mag[sb], sb * sb)
+                                                               fastmod(mshash(LC[t], L.key[rk[k]]), L.mag[sb], sb * sb)
                                                          : c0k[k];
-                    L.smap[cell] = (uint16_t)i;
+                    L.smap[cell] = (uint16_t)rk[k];
                 }
             }
         }
@@ -1248,7 +1258,7 @@ static void launch_fused(const PartArgs& a, const PartOut& o, const Triple* C, u
     hipLaunchKernelGGL(k_zero_words, 1, 64, 0, st, a.sqQ, (uint64_t)1);
     const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q, o.qend, o.qcap};
     FKS_TIMED("fks_part_final", st,
-              hipLaunchKernelGGL((k_pfinal<AUX, STR, false, true>), Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+              hipLaunchKernelGGL((k_pfinal<AUX, STR, false, true>), Q, kPB, 0, st, o.keys, o.vals,
                                  AUX ? o.aux : nullptr, AUX ? o.aux_is_pos : 1, a.n, a.A, a.magic, o.qbeg, a.cbase,
                                  a.sizes, a.G, C, T, header, slots, flags, ctx_off, ctx_bytes, nullptr, nullptr,
                                  reject, cap, fa));
@@ -1269,17 +1279,17 @@ int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T
     }
     if (a.aux && a.str)
         FKS_TIMED("fks_part_final", st,
-                  hipLaunchKernelGGL((k_pfinal<true, true>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                  hipLaunchKernelGGL((k_pfinal<true, true>), o.plan.Q, kPB, 0, st, o.keys, o.vals,
                                      o.aux, o.aux_is_pos, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T,
                                      header, slots, flags, ctx_off, ctx_bytes, given_t, nullptr, reject, cap));
     else if (a.aux)
         FKS_TIMED("fks_part_final", st,
-                  hipLaunchKernelGGL((k_pfinal<true, false>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                  hipLaunchKernelGGL((k_pfinal<true, false>), o.plan.Q, kPB, 0, st, o.keys, o.vals,
                                      o.aux, o.aux_is_pos, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T,
                                      header, slots, flags, nullptr, nullptr, given_t, nullptr, reject, cap));
     else
         FKS_TIMED("fks_part_final", st,
-                  hipLaunchKernelGGL((k_pfinal<false, false>), o.plan.Q, kPB, sizeof(Triple) * T, st, o.keys, o.vals,
+                  hipLaunchKernelGGL((k_pfinal<false, false>), o.plan.Q, kPB, 0, st, o.keys, o.vals,
                                      nullptr, 1, a.n, a.A, a.magic, a.offQ, a.cbase, a.sizes, a.G, C, T, header,
                                      slots, flags, nullptr, nullptr, given_t, nullptr, reject, cap));
     hipError_t e = hipGetLastError();
@@ -1342,7 +1352,7 @@ int wide_build(const uint64_t* d_keys, const uint32_t* d_vals, const WideSeg* se
                                  segs));
     hipLaunchKernelGGL(k_wbases, (nseg + 255) / 256, 256, 0, st, sqQ, segs, nseg, cbase, flags);
     FKS_TIMED("fks_wide_final", st,
-              hipLaunchKernelGGL((k_pfinal<false, false, true>), Q, kPB, sizeof(Triple) * T, st, k2, v2, nullptr, 1,
+              hipLaunchKernelGGL((k_pfinal<false, false, true>), Q, kPB, 0, st, k2, v2, nullptr, 1,
                                  nkeys, A0, 0ull, offQ, cbase, sizes, 0ull, Cpool, T, hdr_pool, slot_pool, flags,
                                  nullptr, nullptr, nullptr, segs));
     const hipError_t e = hipGetLastError();
