@@ -32,7 +32,8 @@ constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
 // word travels (larger records, 4096-record tiles)
 constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 8, kPScatterItemsAux = 4;
 constexpr uint32_t kBins = 256;               // bins per scatter pass
-constexpr uint32_t kFinalKeyCap = 1280;       // keys of one partition held in LDS (mean 1024, sd 32)
+constexpr uint32_t kFinalKeyCap = 1248;       // keys of one partition held in LDS (mean 1024, sd 32)
+constexpr uint32_t kLdsTrials = 16;          // level-two triples held in the final pass's LDS (larger trials are rare)
 constexpr uint32_t kFinalCellCap = 3072;      // cells of one partition staged in LDS (mean <= 2048, sd ~106)
 constexpr uint32_t kGroupsPerPart = kPartBuckets / 8;
 
@@ -469,6 +470,7 @@ struct FinalLds {
     uint32_t fl[kPartBuckets / 32];     // buckets where trial 0 collides
     uint16_t hard[kFinalKeyCap / 2];   // buckets of two or more keys that trial 0 does not place
     uint64_t mag[16];             // remainder magic of s^2, s = 0..15
+    Triple tri[kLdsTrials];       // the first level-two triples (larger trials are rare)
     uint32_t nhard;
     uint32_t wsum[2][kPB / 64];
     uint32_t flags[3];   // exhausted, dup, max_t
@@ -513,11 +515,13 @@ __device__ __forceinline__ uint32_t wave_max16(uint32_t v) {
 // smallest trial from t0 on for a bucket of 2..8 keys held in registers: one 64-bit
 // occupancy mask, remainders by multiplication.  smax: the largest bucket among the
 // wave's active lanes; key slots beyond it are skipped by the whole wave
-__device__ __forceinline__ uint32_t min_trial_small(const Triple* C, uint32_t T, uint32_t s, const uint64_t (&kx)[8],
+// (tri(t): triple t)
+template <typename TriAt>
+__device__ __forceinline__ uint32_t min_trial_small(TriAt tri, uint32_t T, uint32_t s, const uint64_t (&kx)[8],
                                                     uint64_t M, uint32_t t0 = 0, uint32_t smax = 8) {
     const uint32_t s2 = s * s;
     for (uint32_t t = t0; t < T; ++t) {
-        const Triple c = C[t];
+        const Triple c = tri(t);
         uint64_t m = 0;
         bool collide = false;
 #pragma unroll
@@ -610,8 +614,7 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
     }
     bool fast = FUSED ? keys_fit : keys_fit && Sq <= kFinalCellCap;
     // the partition's records go in flight first; the set-up below overlaps their latency
-    constexpr uint32_t KPT = kFinalKeyCap / kPB;
-    static_assert(kFinalKeyCap % kPB == 0, "whole records per thread");
+    constexpr uint32_t KPT = (kFinalKeyCap + kPB - 1) / kPB;   // record slots per thread
     uint64_t xk[KPT];
     uint32_t vk[KPT], ak[KPT];
     if (fast) {
@@ -625,9 +628,11 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
             }
         }
     }
-    // the T level-two triples stay in global memory: a wave's search reads one triple at a
-    // time (one address per wave), and the placement's reads are cached
+    // the first kLdsTrials level-two triples are staged in LDS; larger trials read theirs
+    // from global memory
     const Triple* const LC = Cg;
+    for (uint32_t t = tid; t < kLdsTrials && t < T; t += kPB) L.tri[t] = Cg[t];
+    auto tri = [&](uint32_t t) { return t < kLdsTrials ? L.tri[t] : Cg[t]; };
     if (!FUSED) {
         for (uint32_t g = tid; g < kGroupsPerPart; g += kPB)
             L.words[g] = (uint64_t)qh * kGroupsPerPart + g < G ? sizes[(uint64_t)q * kGroupsPerPart + g] : 0u;
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
         // key owns its bucket's single cell.  Every key of a larger bucket tries trial 0 at
         // once: the second key to claim a cell marks its bucket as colliding, and only those
         // buckets are searched below.
-        const Triple c0t = LC[0];
+        const Triple c0t = L.tri[0];
 #pragma unroll
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
@@ -791,6 +796,14 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                 const uint32_t s = nib(w, kk);
                 const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
                 const uint32_t slot = L.gks[g] + prefix_cnt(w, kk) + rk[k];
+                if (s >= 2) {
+                    // the key of rank r marks cells [r*s, r*s + s) of its bucket with the
+                    // bucket's first cell; placement below overwrites the cells keys take, and
+                    // the write-out resolves a cell still marked to the bucket's lowest
+                    // occupied cell (the fill rule)
+                    const uint32_t from = off + rk[k] * s;
+                    for (uint32_t u = 0; u < s; ++u) L.smap[from + u] = (uint16_t)(0x8000u | off);
+                }
                 rk[k] = slot;
                 L.key[slot] = xk[k];
                 L.val[slot] = vk[k];
@@ -811,21 +824,15 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
             }
         }
         __syncthreads();
-        // Trials: a bucket that trial 0 places keeps t = 0 (tb is zero).  Every cell of
-        // a bucket of two or more keys is marked with the bucket's first cell; the keys
-        // overwrite their own cells below, and the write-out resolves a cell still
-        // marked to the bucket's lowest occupied cell (the fill rule).
-        for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
-            const uint32_t g = b >> 3, kk = b & 7u, w = L.words[g];
-            const uint32_t sb = nib(w, kk);
-            if (sb < 2) continue;
-            if (given_t) {
+        // Trials: a bucket that trial 0 places keeps t = 0 (tb is zero); given trials (the
+        // rounds schedule) are taken as they are
+        if (given_t) {
+            for (uint32_t b = tid; b < kPartBuckets; b += kPB) {
+                if (nib(L.words[b >> 3], b & 7u) < 2) continue;
                 const uint32_t t = given_t[(uint64_t)q * kPartBuckets + b];
                 L.tb[b] = (uint8_t)t;
                 if (t) atomicMax(&L.flags[2], t);
             }
-            const uint32_t off = L.gbase[g] + prefix_sq(w, kk);
-            for (uint32_t p = 0; p < sb * sb; ++p) L.smap[off + p] = (uint16_t)(0x8000u | off);
         }
         // the colliding buckets, one lane each, trials from 1 on with the keys in registers;
         // bucket j goes to lane j / 4 of wave j % 4, so that all four SIMDs search (a packed
@@ -842,7 +849,7 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                 uint64_t kx[8];
 #pragma unroll
                 for (uint32_t i = 0; i < 8; ++i) kx[i] = i < sb ? L.key[kst + i] : 0;
-                t = min_trial_small(LC, T, sb, kx, L.mag[sb], 1, smax);
+                t = min_trial_small(tri, T, sb, kx, L.mag[sb], 1, smax);
             } else {
                 t = min_trial(LC, T, sb, [&](uint32_t i) { return L.key[kst + i]; }, 1);
             }
@@ -874,7 +881,7 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                 if (sb >= 2) {
                     const uint32_t t = L.tb[lb];
                     const uint32_t cell = (t || given_t) ? L.gbase[g] + prefix_sq(w, kk) +
-                                                               fastmod(mshash(LC[t], L.key[rk[k]]), L.mag[sb], sb * sb)
+                                                               fastmod(mshash(tri(t), L.key[rk[k]]), L.mag[sb], sb * sb)
                                                          : c0k[k];
                     L.smap[cell] = (uint16_t)rk[k];
                 }
