@@ -276,15 +276,16 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
                                          M->ctx_bytes, M->ctx_nbytes, n, beta, y, ctrl));
             a.keys = y;
         }
-        PartOut o;
-        if ((rc = part_prepare(a, st, o))) break;
-        // the attempt's level-two triples travel while the passes run
+        // the attempt's level-two triples go first: the copy runs while the passes' launches
+        // are still being issued
         for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
         if (hipError_t e = hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st);
             e != hipSuccess) {
             rc = hip_fail(e);
             break;
         }
+        PartOut o;
+        if ((rc = part_prepare(a, st, o))) break;
         if (direct) {
             // the final pass follows the size pass without a host round trip; the host waits
             // once per attempt, for the outcome

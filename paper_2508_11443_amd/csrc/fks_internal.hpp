@@ -208,7 +208,8 @@ __host__ __device__ inline uint32_t group_t(const Group& g, uint32_t k) {
 
 // A bucket of one key always takes trial 0, so its trial byte holds a tag of that key
 // instead: the top 8 bits of the key's trial-0 level-two hash (c0 = the first triple).
-__host__ __device__ inline uint32_t key_tag(const Triple& c0, uint64_t x) { return mshash(c0, x) >> 24; }
+__host__ __device__ inline uint32_t tag_of(uint32_t h0) { return h0 >> 24; }   // h0: the trial-0 hash
+__host__ __device__ inline uint32_t key_tag(const Triple& c0, uint64_t x) { return tag_of(mshash(c0, x)); }
 
 // The cell needle x would occupy in bucket k of group record h, with the level-two
 // triples C of the map.  False when x cannot be in the bucket: the bucket is empty, or it

@@ -238,14 +238,27 @@ __global__ __launch_bounds__(BT) void k_dscatter(const uint64_t* __restrict__ ke
     }
 }
 
-// cursor of fixed-capacity region i starts at i * cap (begin[i] keeps that start)
-__global__ void k_init_cursors(unsigned long long* __restrict__ cursor, uint64_t* __restrict__ begin, uint64_t count,
-                               uint64_t cap) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        cursor[i] = i * cap;
-        if (begin) begin[i] = i * cap;
+// the set-up of the cursor passes in one launch: the cursor of fixed-capacity region i of
+// either pass starts at i * cap (begin[i] keeps that start), and the fused final pass's
+// look-back words and ticket (zw words) start at zero
+__global__ void k_init_cursors(unsigned long long* __restrict__ cur1, uint64_t* __restrict__ beg1, uint64_t count1,
+                               uint64_t cap1, unsigned long long* __restrict__ cur2, uint64_t* __restrict__ beg2,
+                               uint64_t count2, uint64_t cap2, uint32_t* __restrict__ zw, uint64_t nzw,
+                               uint32_t* __restrict__ ticket) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count1 + count2 + nzw; i += stride) {
+        if (i < count1) {
+            cur1[i] = i * cap1;
+            beg1[i] = i * cap1;
+        } else if (i < count1 + count2) {
+            const uint64_t j = i - count1;
+            cur2[j] = j * cap2;
+            beg2[j] = j * cap2;
+        } else {
+            zw[i - count1 - count2] = 0;
+        }
     }
+    if (ticket && blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
 }
 
 
@@ -809,12 +822,13 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                 L.val[slot] = vk[k];
                 if (AUX) L.aux[slot] = ak[k];
                 c0k[k] = off;
+                const uint32_t h0 = mshash(c0t, xk[k]);   // trial 0
                 if (s == 1) {
                     L.smap[off] = (uint16_t)slot;
-                    L.tb[lb] = (uint8_t)key_tag(c0t, xk[k]);   // trial 0; the byte holds the key's tag
+                    L.tb[lb] = (uint8_t)tag_of(h0);   // trial 0; the byte holds the key's tag
                 } else {
                     if (!given_t) {
-                        const uint32_t cell = off + fastmod(mshash(c0t, xk[k]), L.mag[s], s * s);
+                        const uint32_t cell = off + fastmod(h0, L.mag[s], s * s);
                         c0k[k] = cell;
                         const uint32_t bit = 1u << (cell & 31u), bb = 1u << (lb & 31u);
                         if ((atomicOr(&L.occ[cell >> 5], bit) & bit) && !(atomicOr(&L.fl[lb >> 5], bb) & bb))
@@ -1131,6 +1145,7 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     o.qbeg = a.offQ;
     o.qend = a.offQ + 1;
     o.qcap = 0;   // no cap: the counted passes fill their ranges exactly
+    o.prezeroed = false;
     auto count = [&](const uint64_t* kin, const uint64_t* ranges, dim3 grid, uint32_t W, uint32_t shift,
                      uint32_t mask) {
         FKS_TIMED("fks_part_count", st,
@@ -1152,10 +1167,13 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
         o.aux = a.a2;
         o.aux_is_pos = aux ? 0 : 1;
     } else if (P.passes == 2 && a.cursor) {
-        // first-level bins, then partitions, each reserved run by run on the bin's cursor
-        hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.binsA), 256, 0, st, a.cur1, a.begA, (uint64_t)P.binsA,
-                           P.cap1);
-        hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.Q), 256, 0, st, a.cur2, a.begQ, (uint64_t)P.Q, P.capQ);
+        // first-level bins, then partitions, each reserved run by run on the bin's cursor; the
+        // fused final pass's look-back words and ticket are cleared in the same launch
+        const uint64_t nzw = a.fused ? 2 * (uint64_t)P.Q : 0;
+        hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.binsA + P.Q + nzw), 256, 0, st, a.cur1, a.begA,
+                           (uint64_t)P.binsA, P.cap1, a.cur2, a.begQ, (uint64_t)P.Q, P.capQ,
+                           reinterpret_cast<uint32_t*>(a.cbase), nzw, a.fused ? a.sqQ : nullptr);
+        o.prezeroed = a.fused;
         if (aux)
             scatter_cursor<true>(a, a.keys, a.vals, a.aux_in, nullptr, nullptr, 0, dim3(P.W1, 1), P.W1, P.shiftA,
                                  255, a.k1, a.v1, a.a1, a.cur1, P.cap1, st);
@@ -1259,10 +1277,12 @@ static void launch_fused(const PartArgs& a, const PartOut& o, const Triple* C, u
                          uint64_t cap, hipStream_t st) {
     const uint32_t Q = o.plan.Q;
     // the look-back words (in the cell-base scratch) and the ticket (in the partition-sum
-    // scratch) start at zero
-    hipLaunchKernelGGL(k_zero_words, (2 * Q + 255) / 256, 256, 0, st, reinterpret_cast<uint32_t*>(a.cbase),
-                       (uint64_t)2 * Q);
-    hipLaunchKernelGGL(k_zero_words, 1, 64, 0, st, a.sqQ, (uint64_t)1);
+    // scratch) start at zero (the cursor passes' set-up has cleared them already)
+    if (!o.prezeroed) {
+        hipLaunchKernelGGL(k_zero_words, (2 * Q + 255) / 256, 256, 0, st, reinterpret_cast<uint32_t*>(a.cbase),
+                           (uint64_t)2 * Q);
+        hipLaunchKernelGGL(k_zero_words, 1, 64, 0, st, a.sqQ, (uint64_t)1);
+    }
     const FuseArgs fa{a.cbase, a.sqQ, a.S_dev, a.oversize, a.stalled, Q, o.qend, o.qcap};
     FKS_TIMED("fks_part_final", st,
               hipLaunchKernelGGL((k_pfinal<AUX, STR, false, true>), Q, kPB, 0, st, o.keys, o.vals,
@@ -1271,7 +1291,7 @@ static void launch_fused(const PartArgs& a, const PartOut& o, const Triple* C, u
                                  reject, cap, fa));
 }
 
-int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
+int part_finish(const PartArgs& a, PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
                 const uint32_t* reject, uint64_t cap, hipStream_t st) {
     if (a.fused && !given_t) {
@@ -1281,6 +1301,7 @@ int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T
             launch_fused<true, false>(a, o, C, T, header, slots, flags, nullptr, nullptr, reject, cap, st);
         else
             launch_fused<false, false>(a, o, C, T, header, slots, flags, nullptr, nullptr, reject, cap, st);
+        o.prezeroed = false;   // the look-back words are used up: a second run clears them again
         hipError_t e = hipGetLastError();
         return e == hipSuccess ? FKS_OK : hip_fail(e);
     }

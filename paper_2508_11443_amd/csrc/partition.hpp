@@ -90,6 +90,7 @@ struct PartOut {
     const uint64_t* qbeg;       // partition q's records are [qbeg[q], min(qend[q], qbeg[q] + qcap))
     const uint64_t* qend;
     uint64_t qcap;              // 0: no cap (counted passes)
+    bool prezeroed;             // the fused pass's look-back words and ticket are already zero
 };
 
 // Exclusive prefix sum of N u32 counts whose total is below 2^32 (three launches):
@@ -117,7 +118,8 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o);
 // reject: two device words (a bucket above 15 keys, bad string offsets); when either is set
 // the pass writes nothing (nullptr: never).  cap: cells allocated at slots; a partition
 // whose cells would end beyond them writes nothing (the caller compares S with cap).
-int part_finish(const PartArgs& a, const PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
+// The fused pass uses up o's cleared look-back words (o.prezeroed is reset).
+int part_finish(const PartArgs& a, PartOut& o, const Triple* C, uint32_t T, Group* header, Cell* slots,
                 uint32_t* flags, const int64_t* ctx_off, const uint8_t* ctx_bytes, const uint8_t* given_t,
                 const uint32_t* reject, uint64_t cap, hipStream_t st);
 
