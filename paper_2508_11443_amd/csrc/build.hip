@@ -63,6 +63,16 @@ __global__ void k_zero_ctrl(Ctrl* c) {
     }
 }
 
+// an attempt's start: the outcome words cleared and the attempt's T level-two triples
+// written from the seed (the same stream the host draws them from)
+__global__ void k_attempt_setup(Ctrl* c, Triple* C, uint64_t seed, uint32_t r, uint32_t T) {
+    if (threadIdx.x == 0) {
+        c->S = 0;
+        c->oversize = c->bad_input = c->exhausted = c->dup = c->max_t = c->stalled = c->overflow = c->pad = 0;
+    }
+    for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) C[t] = level2_triple(seed, r, t);
+}
+
 // ---- string fingerprints -----------------------------------------------------
 
 // One lane per string.  Offsets are checked here, before any byte is read through them:
@@ -112,15 +122,6 @@ static Readback* pinned_readback() {
     static thread_local Readback* buf = nullptr;
     if (!buf) {
         if (hipHostMalloc((void**)&buf, sizeof(Readback), hipHostMallocDefault) != hipSuccess) buf = nullptr;
-    }
-    return buf;
-}
-
-// pinned staging for an attempt's level-two triples, so their upload is asynchronous
-static Triple* pinned_triples() {
-    static thread_local Triple* buf = nullptr;
-    if (!buf) {
-        if (hipHostMalloc((void**)&buf, sizeof(Triple) * kTMax, hipHostMallocDefault) != hipSuccess) buf = nullptr;
     }
     return buf;
 }
@@ -256,12 +257,6 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         return e == hipSuccess ? FKS_OK : hip_fail(e);
     };
-    Triple* const Ch = pinned_triples();
-    if (!Ch) {
-        drop_slots();
-        release();
-        return FKS_ENOMEM;
-    }
     int rc = FKS_OK;
     for (uint32_t r = 0; r < P.R; ++r) {
         const Triple A = level1_triple(M->seed, r);
@@ -269,20 +264,12 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         a.A = A;
         a.magic = M->magic_n;
         a.keys = d_keys_in;
-        hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
+        hipLaunchKernelGGL(k_attempt_setup, 1, 256, 0, st, ctrl, M->C, M->seed, r, P.T);
         if (bytes) {
             FKS_TIMED("fks_fingerprint", st,
                       hipLaunchKernelGGL(k_fingerprint, grid_for(n, kBlock, 65536), kBlock, 0, st, M->ctx_off,
                                          M->ctx_bytes, M->ctx_nbytes, n, beta, y, ctrl));
             a.keys = y;
-        }
-        // the attempt's level-two triples go first: the copy runs while the passes' launches
-        // are still being issued
-        for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
-        if (hipError_t e = hipMemcpyAsync(M->C, Ch, sizeof(Triple) * P.T, hipMemcpyHostToDevice, st);
-            e != hipSuccess) {
-            rc = hip_fail(e);
-            break;
         }
         PartOut o;
         if ((rc = part_prepare(a, st, o))) break;
@@ -371,6 +358,8 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             hipLaunchKernelGGL(k_fill_u32, grid_for((n + 3) / 4, kBlock, 8192), kBlock, 0, st, (uint32_t*)tb,
                                (n + 3) / 4, 0u);
             bool exhausted = false;
+            Triple Ch[kTMax];   // the rounds pass each round's triple by value
+            for (uint32_t t = 0; t < P.T; ++t) Ch[t] = level2_triple(M->seed, r, t);
             rc = rounds_search(o.keys, n, S, A, M->magic_n, a.sizes, Ch, P.T, tb, &exhausted, st);
             if (rc) {
                 dev_free(cells, st);
