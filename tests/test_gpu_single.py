@@ -130,6 +130,25 @@ def test_forced_retries_match_oracle():
         assert_same_table(m, ref)
 
 
+@pytest.mark.parametrize("s", [8, 12])
+def test_late_trial_bucket_bit_exact(s):
+    """A bucket that no trial below 16 separates (crafted keys, tests/late_trials.py): its
+    search and placement read triples beyond those the final pass stages in LDS (the search of
+    a bucket of at most 8 keys, and of a larger one)."""
+    from tests import late_trials
+    sigma, n = 0x1A7E, 1024
+    announce(f"gpu single u64: late trial, bucket of {s} keys, n={n}")
+    keys = late_trials.keys_with_late_trial(sigma, n, s)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.build_u64(keys, vals, sigma)
+    assert fkscheck.decode_header(ref.export()[0], n)[2][0] >= 16
+    m = gpu_build(keys, vals, sigma)
+    assert_same_table(m, ref)
+    assert m.info()["max_t"] >= 16
+    v, f = gpu_lookup(m, keys)
+    assert f.all() and (v == vals).all()
+
+
 def test_errors():
     fks = _fks()
     announce("gpu single u64: error paths")

@@ -357,3 +357,33 @@ def test_u64_values(n):
     assert [int(h) for h in hi] == [d[int(k)] >> 32 for k in cell_keys]
     with pytest.raises(oracle.OracleError):
         m.lookup(q)   # a 64-bit-value map answers 64-bit lookups only
+
+
+@pytest.mark.parametrize("s", [8, 12])
+def test_late_trial_bucket(s):
+    """A bucket whose keys collide in every one of trials 0..15 (crafted, tests/late_trials.py):
+    make_2 keeps trying and takes the first trial that separates them.  The collisions are
+    re-checked from the fixed readings' hashes, the chosen trial by brute force, and the whole
+    table against the pure-Python restatement byte for byte."""
+    from tests import late_trials
+    sigma, n = 0x1A7E, 1024
+    keys = late_trials.keys_with_late_trial(sigma, n, s)
+    vals = np.arange(n, dtype=np.uint32)
+    m = oracle.build_u64(keys, vals, sigma)
+    assert m.r == 0
+    _, sizes, trials = fkscheck.decode_header(m.export()[0], n)
+    assert sizes[0] == s and trials[0] >= 16
+    a0, a1, b, _ = spec.level1_consts(sigma, 0)
+    mine = [int(x) for x in keys if spec.hash32(a0, a1, b, int(x)) % n == 0]
+    assert len(mine) == s
+
+    def separates(t):
+        c = spec.level2_consts(sigma, 0, t)
+        return len({spec.hash32(*c, x) % (s * s) for x in mine}) == s
+
+    assert not any(separates(t) for t in range(16))
+    assert separates(int(trials[0])) and not any(separates(t) for t in range(int(trials[0])))
+    ref = spec.build_small([int(k) for k in keys], [int(v) for v in vals], sigma)
+    h, c = m.export()
+    assert h.tobytes() == spec.pack_header(ref["sizes"], ref["tbyte"])
+    assert c.tobytes() == spec.pack_cells(ref["cells"])
