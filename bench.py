@@ -332,6 +332,12 @@ def extra_serve(dev, count=4000):
            "saturation": {"requests_per_s": round(sat_rate, 1), **summary(sat),
                           "launches": sat["stats"]["lookup_launches"],
                           "graph_replays": sat["stats"]["graph_replays"]}}
+    # the same closed-loop replay with plain launches instead of graph replays
+    plain, outs = serve.run(wl, budget, closed_loop=True, graphs=False)
+    ok = ok and serve.check(wl, outs, plain["status"])
+    out["saturation_plain_launches"] = {"requests_per_s": round(count / (plain["span_ms"] * 1e-3), 1),
+                                        **summary(plain), "launches": plain["stats"]["lookup_launches"],
+                                        "graph_replays": plain["stats"]["graph_replays"]}
     # open-loop replays: the stream's own rate is 1000 requests/s; scale it to each target
     sweep = {}
     best = None

@@ -365,8 +365,10 @@ int fks_batch_set_schedule(uint32_t M, uint64_t total_keys, uint32_t schedule);
  * A request loop over resident maps (not in the paper; it turns the map of
  * Sections 2-3 into a service).  Builds are admitted against a device-memory
  * budget (an estimate of c*n cells per pending build; idle maps are evicted
- * least recently used first when the budget would be exceeded) and run one at
- * a time on the server's build stream.  Lookup requests of any size that are
+ * least recently used first when the budget would be exceeded) and run on two
+ * build workers, each with its own stream, so two builds can be in flight (a
+ * build waits for admission while the other worker's build still holds its
+ * reservation).  Lookup requests of any size that are
  * queued while other work runs are coalesced into one multi-request launch on
  * the lookup stream, replayed from a HIP graph captured per (ring slot, grid
  * size); so lookups overlap builds on the device.  Results do not depend on
@@ -377,7 +379,7 @@ int fks_batch_set_schedule(uint32_t M, uint64_t total_keys, uint32_t schedule);
  *   that failed to build, or was evicted, complete with that error status.
  *   flags: bit 0 disables graph replay (plain launches).
  *   Device memory: fks_server_create reserves one slab (the budget, plus room
- *   for the running build's scratch: 32 bytes for each key the budget admits)
+ *   for the running builds' scratch: 32 bytes for each key the budget admits)
  *   and every map and build scratch of the server is carved from it, so no
  *   request waits on the driver's allocator; fks_server_create fails with
  *   FKS_ENOMEM when the slab cannot be reserved.

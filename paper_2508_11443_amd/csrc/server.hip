@@ -29,6 +29,7 @@ namespace fks {
 constexpr uint32_t kTile = 1024;          // needles per tile: 256 threads x 4
 constexpr uint32_t kMaxReqPerLaunch = 256;
 constexpr int kRing = 4;                  // lookup launches in flight
+constexpr int kBuildWorkers = 2;          // builds in flight (each worker thread has its own stream)
 
 struct alignas(16) LReq {
     const Group* header;
@@ -176,7 +177,7 @@ struct fks_server {
     uint64_t budget;
     fks_params params;
     int device;
-    hipStream_t build_st = nullptr, lookup_st = nullptr;
+    hipStream_t build_st[kBuildWorkers] = {}, lookup_st = nullptr;
     // state guarded by mu
     std::mutex mu;
     std::condition_variable cv_build, cv_lookup, cv_done;
@@ -222,7 +223,7 @@ struct fks_server {
     bool use_graphs = true;
     hipEvent_t ev[kRing] = {};
     std::map<std::pair<int, uint32_t>, hipGraphExec_t> graphs;   // (ring slot, grid class)
-    std::thread build_thr, lookup_thr;
+    std::thread build_thr[kBuildWorkers], lookup_thr;
     // device memory of the maps and of the builds' scratch
     fks::Arena arena;
     fks_allocator alloc{};
@@ -277,27 +278,34 @@ static void finish_req(fks_server* S, uint64_t id, int status, double t) {
     if (t > S->last_done) S->last_done = t;
 }
 
-static void build_loop(fks_server* S) {
+// build worker w (of kBuildWorkers, each on its own stream): takes the oldest queued build,
+// waits until its reservation is admitted, builds it
+static void build_loop(fks_server* S, int w) {
     (void)hipSetDevice(S->device);
+    const hipStream_t st = S->build_st[w];
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         S->cv_build.wait(lk, [&] { return S->stop || !S->build_q.empty(); });
         if (S->stop) return;
         const uint64_t id = S->build_q.front();
+        S->build_q.pop_front();
         auto& rq = S->reqs[id];
         const uint64_t est = estimate_bytes(rq.n, S->params);
         // admission: wait until the reservation fits, evicting idle maps; a build larger
         // than the whole budget fails at once and leaves the resident maps alone
         while (est <= S->budget && !make_room(S, est)) {
-            // room can still appear once the lookups pinning resident maps drain
+            // room can still appear once the lookups pinning resident maps drain, or once the
+            // other worker's build ends (its reservation becomes a map that can be evicted)
             uint64_t ready_bytes = 0;
-            for (auto& ms : S->maps)
+            bool building = false;
+            for (auto& ms : S->maps) {
                 if (ms.state == 2) ready_bytes += ms.bytes;
-            if (S->used - ready_bytes + est > S->budget || S->stop) break;
+                building = building || ms.state == 1;
+            }
+            if ((!building && S->used - ready_bytes + est > S->budget) || S->stop) break;
             S->cv_build.wait_for(lk, std::chrono::milliseconds(1));
         }
         if (S->stop) return;
-        S->build_q.pop_front();
         auto& slot = S->maps[rq.map_id];
         if (S->used + est > S->budget) {
             slot.state = 3;
@@ -318,8 +326,8 @@ static void build_loop(fks_server* S) {
         lk.unlock();
         fks_map* m = nullptr;
         // the build reads the keys only after the submitter's stream has written them
-        int rc = ready ? (hipStreamWaitEvent(S->build_st, ready, 0) == hipSuccess ? FKS_OK : FKS_EHIP) : FKS_OK;
-        if (rc == FKS_OK) rc = fks_build_u64(keys, vals, n, seed, &p, &S->alloc, S->build_st, &m);
+        int rc = ready ? (hipStreamWaitEvent(st, ready, 0) == hipSuccess ? FKS_OK : FKS_EHIP) : FKS_OK;
+        if (rc == FKS_OK) rc = fks_build_u64(keys, vals, n, seed, &p, &S->alloc, st, &m);
         const double t = now_ms();
         lk.lock();
         S->used -= est;
@@ -510,7 +518,8 @@ extern "C" int fks_server_create(uint64_t budget_bytes, const fks_params* params
     S->use_graphs = (flags & 1u) == 0;
     int rc = FKS_OK;
     hipError_t e = hipGetDevice(&S->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->build_st, hipStreamNonBlocking);
+    for (int w = 0; w < kBuildWorkers && e == hipSuccess; ++w)
+        e = hipStreamCreateWithFlags(&S->build_st[w], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->lookup_st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->capture_st, hipStreamNonBlocking);
     // the arena: the budget for resident maps, plus room for the running build's scratch
@@ -536,14 +545,15 @@ extern "C" int fks_server_create(uint64_t budget_bytes, const fks_params* params
             if (S->d_tab[k]) (void)hipFree(S->d_tab[k]);
             if (S->ev[k]) (void)hipEventDestroy(S->ev[k]);
         }
-        if (S->build_st) (void)hipStreamDestroy(S->build_st);
+        for (int w = 0; w < kBuildWorkers; ++w)
+            if (S->build_st[w]) (void)hipStreamDestroy(S->build_st[w]);
         if (S->lookup_st) (void)hipStreamDestroy(S->lookup_st);
         if (S->capture_st) (void)hipStreamDestroy(S->capture_st);
         if (S->arena.base) (void)hipFree(S->arena.base);
         delete S;
         return rc;
     }
-    S->build_thr = std::thread(build_loop, S);
+    for (int w = 0; w < kBuildWorkers; ++w) S->build_thr[w] = std::thread(build_loop, S, w);
     S->lookup_thr = std::thread(lookup_loop, S);
     *out = S;
     return FKS_OK;
@@ -589,7 +599,7 @@ extern "C" int fks_server_submit_build(fks_server* S, const uint64_t* d_keys, co
     S->build_q.push_back(id);
     if (req_id) *req_id = id;
     if (map_id) *map_id = r.map_id;
-    S->cv_build.notify_one();
+    S->cv_build.notify_all();   // a worker waiting for admission must not take the only wake-up
     return FKS_OK;
 }
 
@@ -704,10 +714,10 @@ extern "C" void fks_server_destroy(fks_server* S) {
     }
     S->cv_build.notify_all();
     S->cv_lookup.notify_all();
-    S->build_thr.join();
+    for (int w = 0; w < kBuildWorkers; ++w) S->build_thr[w].join();
     S->lookup_thr.join();
     (void)hipStreamSynchronize(S->lookup_st);
-    (void)hipStreamSynchronize(S->build_st);
+    for (int w = 0; w < kBuildWorkers; ++w) (void)hipStreamSynchronize(S->build_st[w]);
     for (auto& kv : S->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& m : S->maps)
         if (m.map) fks_destroy(m.map);
@@ -716,7 +726,7 @@ extern "C" void fks_server_destroy(fks_server* S) {
         (void)hipFree(S->d_tab[k]);
         (void)hipEventDestroy(S->ev[k]);
     }
-    (void)hipStreamDestroy(S->build_st);
+    for (int w = 0; w < kBuildWorkers; ++w) (void)hipStreamDestroy(S->build_st[w]);
     (void)hipStreamDestroy(S->lookup_st);
     (void)hipStreamDestroy(S->capture_st);
     (void)hipFree(S->arena.base);
