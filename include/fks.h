@@ -365,9 +365,9 @@ int fks_batch_set_schedule(uint32_t M, uint64_t total_keys, uint32_t schedule);
  * A request loop over resident maps (not in the paper; it turns the map of
  * Sections 2-3 into a service).  Builds are admitted against a device-memory
  * budget (an estimate of c*n cells per pending build; idle maps are evicted
- * least recently used first when the budget would be exceeded) and run on two
- * build workers, each with its own stream, so two builds can be in flight (a
- * build waits for admission while the other worker's build still holds its
+ * least recently used first when the budget would be exceeded) and run on three
+ * build workers, each with its own stream, so three builds can be in flight (a
+ * build waits for admission while another worker's build still holds its
  * reservation).  Lookup requests of any size that are
  * queued while other work runs are coalesced into one multi-request launch on
  * the lookup stream, replayed from a HIP graph captured per (ring slot, grid

@@ -31,6 +31,7 @@ constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
 // per bin, 101 KB of LDS: one workgroup and four waves per SIMD on a CU), or x 4 when an aux
 // word travels (larger records, 4096-record tiles)
 constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 8, kPScatterItemsAux = 4;
+constexpr uint64_t kWorkerKeys = 2ull * kPScatterThreads * kPScatterItems;   // keys per scatter worker: two tiles
 constexpr uint32_t kBins = 256;               // bins per scatter pass
 constexpr uint32_t kFinalKeyCap = 1248;       // keys of one partition held in LDS (mean 1024, sd 32)
 constexpr uint32_t kLdsTrials = 16;          // level-two triples held in the final pass's LDS (larger trials are rare)
@@ -1055,7 +1056,7 @@ PartPlan part_plan(uint64_t n) {
     while ((1ull << bits) < P.Q) ++bits;
     P.bits_q = bits;
     auto clampu = [](uint64_t v, uint64_t lo, uint64_t hi) { return (uint32_t)(v < lo ? lo : v > hi ? hi : v); };
-    P.W1 = clampu((n + 4 * kPTile - 1) / (4 * kPTile), 1, 4096);
+    P.W1 = clampu((n + kWorkerKeys - 1) / (kWorkerKeys), 1, 4096);
     if (P.Q <= 1) {
         P.passes = 0;
     } else if (bits <= 8) {
@@ -1066,7 +1067,7 @@ PartPlan part_plan(uint64_t n) {
         P.shiftA = bits - 8;
         P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
         P.bitsB = P.shiftA;
-        P.W2 = clampu((n / P.binsA + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
+        P.W2 = clampu((n / P.binsA + kWorkerKeys - 1) / (kWorkerKeys), 1, 64);
         // regions of the cursor form: a first-level bin covers 2^shiftA partitions of 1024
         // buckets and a partition 1024 buckets; with n keys in n buckets the keys of B buckets
         // number B on average with a standard deviation of about sqrt(B), and the regions hold
@@ -1084,8 +1085,8 @@ PartPlan part_plan(uint64_t n) {
         P.bitsC = bits - 16;
         P.bitsB = 8;
         P.binsAB = (uint32_t)((P.Q + (1u << P.bitsC) - 1) >> P.bitsC);
-        P.W2 = clampu((n / P.binsA + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
-        P.W3 = clampu((n / P.binsAB + 4 * kPTile - 1) / (4 * kPTile), 1, 64);
+        P.W2 = clampu((n / P.binsA + kWorkerKeys - 1) / (kWorkerKeys), 1, 64);
+        P.W3 = clampu((n / P.binsAB + kWorkerKeys - 1) / (kWorkerKeys), 1, 64);
     }
     uint64_t m1 = (uint64_t)kBins * P.W1;
     uint64_t m2 = P.passes >= 2 ? (uint64_t)P.binsA * kBins * P.W2 : 0;

@@ -29,7 +29,7 @@ namespace fks {
 constexpr uint32_t kTile = 1024;          // needles per tile: 256 threads x 4
 constexpr uint32_t kMaxReqPerLaunch = 256;
 constexpr int kRing = 4;                  // lookup launches in flight
-constexpr int kBuildWorkers = 2;          // builds in flight (each worker thread has its own stream)
+constexpr int kBuildWorkers = 3;          // builds in flight (each worker thread has its own stream)
 
 struct alignas(16) LReq {
     const Group* header;
