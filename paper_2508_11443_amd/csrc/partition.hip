@@ -2,9 +2,9 @@
 //
 // Buckets are cut into partitions of 1024 consecutive buckets (q = j >> 10).
 // Keys are moved into partition order by one to three coalescing radix passes
-// over q (at most 8 bits, 256 bins, per pass, so every 8192-record tile writes
-// runs of about 32 records per bin; every worker's offsets come from a scanned
-// count matrix), then every partition is finished by one workgroup that holds
+// over q (at most 8 bits, 256 bins, per pass, so every 12288-record tile writes
+// runs of about 48 records per bin; every worker's offsets come from a scanned
+// count matrix, or from cursors on fixed-capacity regions), then every partition is finished by one workgroup that holds
 // its ~1024 keys in LDS: ranks from an LDS histogram, scan of the 128 group
 // statistics, grouping, the per-bucket level-two search of make_2, and the
 // coalesced write of the partition's contiguous cells and group headers.  Only
@@ -27,10 +27,10 @@ namespace fks {
 constexpr uint32_t kPB = 256;                 // threads per block, partition passes
 constexpr uint32_t kPItems = 16;              // keys per thread per tile
 constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
-// scatter tiles of the single-map passes: 1024 threads x 8 records (8192 records, runs of ~32
-// per bin, 101 KB of LDS: one workgroup and four waves per SIMD on a CU), or x 4 when an aux
+// scatter tiles of the single-map passes: 1024 threads x 12 records (12288 records, runs of ~48
+// per bin, 149 KB of LDS: one workgroup and four waves per SIMD on a CU), or x 4 when an aux
 // word travels (larger records, 4096-record tiles)
-constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 8, kPScatterItemsAux = 4;
+constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 12, kPScatterItemsAux = 4;
 constexpr uint64_t kWorkerKeys = 2ull * kPScatterThreads * kPScatterItems;   // keys per scatter worker: two tiles
 constexpr uint32_t kBins = 256;               // bins per scatter pass
 constexpr uint32_t kFinalKeyCap = 1248;       // keys of one partition held in LDS (mean 1024, sd 32)
