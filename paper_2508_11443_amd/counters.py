@@ -43,7 +43,7 @@ GIB = 1 << 30
 # without "void ", "fks::", argument list and spaces; source file)
 KERNELS = {
     "fks_lookup_u64": ("k_lookup_u64<true,true,false>", "paper_2508_11443_amd/csrc/lookup.hip"),
-    "fks_part_scatter": ("k_dscatter<false,8u,1024u,true>", "paper_2508_11443_amd/csrc/partition.hip"),
+    "fks_part_scatter": ("k_dscatter<false,12u,1024u,true>", "paper_2508_11443_amd/csrc/partition.hip"),
     "fks_part_final": ("k_pfinal<false,false,false,true>", "paper_2508_11443_amd/csrc/partition.hip"),
 }
 
