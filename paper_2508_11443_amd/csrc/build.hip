@@ -203,35 +203,54 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
     const size_t o_offA = carve(8 * 257), o_offQ = carve(8 * ((size_t)Q + 1)), o_sqQ = carve(4 * (size_t)Q);
     const size_t o_offAB = plan.passes == 3 ? carve(8 * ((size_t)plan.binsAB + 1)) : 0;
     const size_t o_cbase = carve(8 * ((size_t)Q + 1)), o_sizes = carve(4 * (size_t)Q * (kPartBuckets / 8));
-    char* base = (char*)dev_alloc(total, st);
-    if (!base) return FKS_ENOMEM;
-    owned.push_back(base);
-    if (plan.passes >= 2) {
-        a.k1 = (uint64_t*)(base + o_k1);
-        a.v1 = (uint32_t*)(base + o_v1);
-        if (carry) a.a1 = (uint32_t*)(base + o_a1);
-    }
-    if (plan.passes >= 1) {
-        a.k2 = (uint64_t*)(base + o_k2);
-        a.v2 = (uint32_t*)(base + o_v2);
-        if (carry) a.a2 = (uint32_t*)(base + o_a2);
-    }
-    a.cnt = (uint32_t*)(base + o_cnt);
-    a.off = (uint32_t*)(base + o_off);
-    a.tsum = (uint32_t*)(base + o_tsum);
-    a.tpre = (uint64_t*)(base + o_tpre);
-    a.offA = (uint64_t*)(base + o_offA);
-    if (plan.passes == 3) a.offAB = (uint64_t*)(base + o_offAB);
-    a.offQ = (uint64_t*)(base + o_offQ);
-    a.sqQ = (uint32_t*)(base + o_sqQ);
-    a.cbase = (uint64_t*)(base + o_cbase);
-    a.sizes = (uint32_t*)(base + o_sizes);
-    if (cursor) {
-        a.cur1 = (unsigned long long*)(base + o_cur1);
-        a.cur2 = (unsigned long long*)(base + o_cur2);
-        a.begA = (uint64_t*)(base + o_begA);
-        a.begQ = (uint64_t*)(base + o_begQ);
-    }
+    char* base = nullptr;
+    // points the passes' buffers into the scratch at base
+    auto attach_scratch = [&]() {
+        if (plan.passes >= 2) {
+            a.k1 = (uint64_t*)(base + o_k1);
+            a.v1 = (uint32_t*)(base + o_v1);
+            if (carry) a.a1 = (uint32_t*)(base + o_a1);
+        }
+        if (plan.passes >= 1) {
+            a.k2 = (uint64_t*)(base + o_k2);
+            a.v2 = (uint32_t*)(base + o_v2);
+            if (carry) a.a2 = (uint32_t*)(base + o_a2);
+        }
+        a.cnt = (uint32_t*)(base + o_cnt);
+        a.off = (uint32_t*)(base + o_off);
+        a.tsum = (uint32_t*)(base + o_tsum);
+        a.tpre = (uint64_t*)(base + o_tpre);
+        a.offA = (uint64_t*)(base + o_offA);
+        if (plan.passes == 3) a.offAB = (uint64_t*)(base + o_offAB);
+        a.offQ = (uint64_t*)(base + o_offQ);
+        a.sqQ = (uint32_t*)(base + o_sqQ);
+        a.cbase = (uint64_t*)(base + o_cbase);
+        a.sizes = (uint32_t*)(base + o_sizes);
+        if (cursor) {
+            a.cur1 = (unsigned long long*)(base + o_cur1);
+            a.cur2 = (unsigned long long*)(base + o_cur2);
+            a.begA = (uint64_t*)(base + o_begA);
+            a.begQ = (uint64_t*)(base + o_begQ);
+        }
+    };
+    // (re)takes the scratch and points the passes' buffers into it
+    auto ensure_scratch = [&]() {
+        if (base) return true;
+        base = (char*)dev_alloc(total, st);
+        if (!base) return false;
+        owned.push_back(base);
+        attach_scratch();
+        return true;
+    };
+    auto release_scratch = [&]() {
+        release();
+        base = nullptr;
+    };
+    if (!ensure_scratch()) return FKS_ENOMEM;
+    // with the device's default pool the scratch goes back, in stream order, as soon as its
+    // last reader (the final pass) is queued: the host's wait for the outcome then ends the
+    // call with nothing left to release.  The rare second pass or attempt takes it again.
+    const bool early_release = direct && dev_pool_default();
     a.overflow = &ctrl->overflow;
     a.S_dev = &ctrl->S;
     a.oversize = &ctrl->oversize;
@@ -271,6 +290,10 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
                                          M->ctx_bytes, M->ctx_nbytes, n, beta, y, ctrl));
             a.keys = y;
         }
+        if (!ensure_scratch()) {
+            rc = FKS_ENOMEM;
+            break;
+        }
         PartOut o;
         if ((rc = part_prepare(a, st, o))) break;
         if (direct) {
@@ -279,6 +302,7 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
             if ((rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off, M->ctx_bytes,
                                   nullptr, reject, cap, st)))
                 break;
+            if (early_release) release_scratch();
             if ((rc = readback())) break;
             if (host->bad_input) {
                 rc = FKS_EINVAL;
@@ -308,9 +332,18 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
                     break;
                 }
                 hipLaunchKernelGGL(k_zero_ctrl, 1, 64, 0, st, ctrl);
+                if (!base) {
+                    // the scratch went back early: the partition passes run again into it
+                    if (!ensure_scratch()) {
+                        rc = FKS_ENOMEM;
+                        break;
+                    }
+                    if ((rc = part_prepare(a, st, o))) break;
+                }
                 if ((rc = part_finish(a, o, M->C, P.T, M->header, slots, &ctrl->exhausted, M->ctx_off,
                                       M->ctx_bytes, nullptr, reject, cap, st)))
                     break;
+                if (early_release) release_scratch();
                 if ((rc = readback())) break;
             }
             if (host->exhausted) {

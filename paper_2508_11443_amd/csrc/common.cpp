@@ -37,6 +37,8 @@ static thread_local const fks_allocator* tl_alloc = nullptr;
 AllocScope::AllocScope(const fks_allocator* a) : prev_(tl_alloc) { tl_alloc = a; }
 AllocScope::~AllocScope() { tl_alloc = prev_; }
 
+bool dev_pool_default() { return tl_alloc == nullptr; }
+
 void* dev_alloc(size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 16;
     if (tl_alloc) {

@@ -261,6 +261,9 @@ int hip_fail(hipError_t e);
 // the object was built with), so all of a call's memory comes from one place.
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+// the current call allocates from the device's default pool (hipMallocAsync / hipFreeAsync),
+// whose stream-ordered release may be issued while queued work still uses the memory
+bool dev_pool_default();
 class AllocScope {
   public:
     explicit AllocScope(const fks_allocator* a);

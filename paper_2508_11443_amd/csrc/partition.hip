@@ -28,9 +28,9 @@ constexpr uint32_t kPB = 256;                 // threads per block, partition pa
 constexpr uint32_t kPItems = 16;              // keys per thread per tile
 constexpr uint32_t kPTile = kPB * kPItems;    // 4096 keys per tile
 // scatter tiles of the single-map passes: 1024 threads x 12 records (12288 records, runs of ~48
-// per bin, 149 KB of LDS: one workgroup and four waves per SIMD on a CU), or x 4 when an aux
-// word travels (larger records, 4096-record tiles)
-constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 12, kPScatterItemsAux = 4;
+// per bin, 149 KB of LDS: one workgroup and four waves per SIMD on a CU), or x 8 when an aux
+// word travels (16-byte records, 8192-record tiles, 133 KB)
+constexpr uint32_t kPScatterThreads = 1024, kPScatterItems = 12, kPScatterItemsAux = 8;
 constexpr uint64_t kWorkerKeys = 2ull * kPScatterThreads * kPScatterItems;   // keys per scatter worker: two tiles
 constexpr uint32_t kBins = 256;               // bins per scatter pass
 constexpr uint32_t kFinalKeyCap = 1248;       // keys of one partition held in LDS (mean 1024, sd 32)
