@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
             const uint64_t i = base + threadIdx.x + (uint64_t)k * kLBlock;
-            x[k] = i < m ? q[i] : 0;
+            x[k] = i < m ? __builtin_nontemporal_load(q + i) : 0;   // needles and answers stream
         }
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
@@ -65,17 +65,25 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
         for (int k = 0; k < kQ; ++k) {
             uint32_t p;
             s[k] = cell_of(h[k], kk[k], C, x[k], p) ? 1u : 0u;
-            if (s[k]) c[k] = slots[p];
-            else c[k] = Cell{~x[k], 0, 0};
+            if (s[k]) {
+                // read once per needle: a streaming load, so that the cells do not push the
+                // group records out of the caches
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) + p);
+                c[k] = Cell{(uint64_t)v.x | ((uint64_t)v.y << 32), v.z, v.w};
+            } else {
+                c[k] = Cell{~x[k], 0, 0};
+            }
         }
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
             const uint64_t i = base + threadIdx.x + (uint64_t)k * kLBlock;
             if (i < m) {
                 const bool hit = s[k] && c[k].key == x[k];
-                if (WANT_VALS && V64) vals64[i] = hit ? ((uint64_t)c[k].aux << 32) | c[k].val : missing64;
-                if (WANT_VALS && !V64) vals[i] = hit ? c[k].val : missing;
-                if (WANT_FOUND) found[i] = hit ? 1 : 0;
+                if (WANT_VALS && V64)
+                    __builtin_nontemporal_store(hit ? ((uint64_t)c[k].aux << 32) | c[k].val : missing64, vals64 + i);
+                if (WANT_VALS && !V64) __builtin_nontemporal_store(hit ? c[k].val : missing, vals + i);
+                if (WANT_FOUND) __builtin_nontemporal_store((uint8_t)(hit ? 1 : 0), found + i);
             }
         }
     }
