@@ -33,6 +33,9 @@ struct alignas(16) Group {
 };
 
 // 16-byte cell.
+// four dwords: the unit of the 16-byte streaming loads and stores of cells and group records
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 struct alignas(16) Cell {
     uint64_t key;
     uint32_t val;

@@ -68,7 +68,6 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
             if (s[k]) {
                 // read once per needle: a streaming load, so that the cells do not push the
                 // group records out of the caches
-                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
                 const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) + p);
                 c[k] = Cell{(uint64_t)v.x | ((uint64_t)v.y << 32), v.z, v.w};
             } else {

@@ -636,8 +636,10 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
         for (uint32_t k = 0; k < KPT; ++k) {
             const uint32_t i = tid + k * kPB;
             if (i < nq) {
-                xk[k] = keys[k0 + i];
-                vk[k] = vals[k0 + i];
+                // streaming loads: each record is read once here (and each cell and group
+                // record below written once), so none of them displaces the caches' other data
+                xk[k] = __builtin_nontemporal_load(keys + k0 + i);
+                vk[k] = __builtin_nontemporal_load(vals + k0 + i);
                 if (AUX) ak[k] = aux_is_pos ? (uint32_t)(k0 + i) : aux[k0 + i];
             }
         }
@@ -934,7 +936,8 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                 c.key = L.key[i];
                 c.val = L.val[i];
                 c.aux = AUX ? L.aux[i] : 0u;
-                slots[c0 + p] = c;
+                const u32x4 w = {(uint32_t)c.key, (uint32_t)(c.key >> 32), c.val, c.aux};
+                __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(slots) + c0 + p);
             }
         }
     } else {
@@ -1022,7 +1025,8 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                      ((uint32_t)L.tb[8 * g + 3] << 24);
             h.t_hi = (uint32_t)L.tb[8 * g + 4] | ((uint32_t)L.tb[8 * g + 5] << 8) |
                      ((uint32_t)L.tb[8 * g + 6] << 16) | ((uint32_t)L.tb[8 * g + 7] << 24);
-            header[gg] = h;
+            const u32x4 hw = {h.base, h.sizes, h.t_lo, h.t_hi};
+            __builtin_nontemporal_store(hw, reinterpret_cast<u32x4*>(header) + gg);
         }
     }
     if (tid == 0) {
