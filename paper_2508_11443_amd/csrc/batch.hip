@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_batch_lookup(const LDesc* __restrict__ 
         for (int k = 0; k < Q; ++k) {
             uint32_t p;
             if (s[k]) s[k] = cell_of(h[k], kk[k], Cpool + (uint64_t)id[k] * d[k].T, x[k], p) ? 1u : 0u;
-            if (s[k]) cl[k] = slot_pool[d[k].slot_off + p];
+            if (s[k]) cl[k] = load_cell_once(slot_pool + d[k].slot_off + p);
         }
 #pragma unroll
         for (int k = 0; k < Q; ++k) {

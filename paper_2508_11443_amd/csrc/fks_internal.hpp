@@ -42,6 +42,17 @@ struct alignas(16) Cell {
     uint32_t aux;
 };
 
+// A cell touched once by a kernel (a lookup's probe, a pass over the table): a streaming
+// (non-temporal) access, which leaves the caches to data that is read again.
+__device__ __forceinline__ Cell load_cell_once(const Cell* p) {
+    const u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    return Cell{(uint64_t)w.x | ((uint64_t)w.y << 32), w.z, w.w};
+}
+__device__ __forceinline__ void store_cell_once(Cell* p, const Cell& c) {
+    const u32x4 w = {(uint32_t)c.key, (uint32_t)(c.key >> 32), c.val, c.aux};
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(p));
+}
+
 // ---- SplitMix64 (Steele, Lea & Flood 2014), counter based --------------------
 __host__ __device__ inline uint64_t sm_fin(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -65,14 +65,9 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_u64(const Group* __restrict_
         for (int k = 0; k < kQ; ++k) {
             uint32_t p;
             s[k] = cell_of(h[k], kk[k], C, x[k], p) ? 1u : 0u;
-            if (s[k]) {
-                // read once per needle: a streaming load, so that the cells do not push the
-                // group records out of the caches
-                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) + p);
-                c[k] = Cell{(uint64_t)v.x | ((uint64_t)v.y << 32), v.z, v.w};
-            } else {
-                c[k] = Cell{~x[k], 0, 0};
-            }
+            // read once per needle: a streaming load, so that the cells do not push the group
+            // records out of the caches
+            c[k] = s[k] ? load_cell_once(slots + p) : Cell{~x[k], 0, 0};
         }
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
@@ -122,7 +117,7 @@ __global__ __launch_bounds__(kLBlock) void k_lookup_bytes(
         uint32_t v = missing;
         uint32_t p;
         if (cell_of(h, k, C, y, p)) {
-            const Cell c = slots[p];
+            const Cell c = load_cell_once(slots + p);
             if (c.key == y) {
                 const int64_t ka = koff[c.aux], kb = koff[c.aux + 1];
                 if ((uint64_t)(kb - ka) == len) {

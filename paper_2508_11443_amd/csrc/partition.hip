@@ -936,8 +936,7 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(kFinalWaves
                 c.key = L.key[i];
                 c.val = L.val[i];
                 c.aux = AUX ? L.aux[i] : 0u;
-                const u32x4 w = {(uint32_t)c.key, (uint32_t)(c.key >> 32), c.val, c.aux};
-                __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(slots) + c0 + p);
+                store_cell_once(slots + c0 + p, c);
             }
         }
     } else {

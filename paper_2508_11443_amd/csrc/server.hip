@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_lookup_multi(const LTab* __restrict__ t
         for (int k = 0; k < 4; ++k) {
             uint32_t p;
             if (s[k]) s[k] = cell_of(h[k], kk[k], C, x[k], p) ? 1u : 0u;
-            if (s[k]) c[k] = R.slots[p];
+            if (s[k]) c[k] = load_cell_once(R.slots + p);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {

@@ -68,11 +68,11 @@ __global__ __launch_bounds__(kVBlock) void k_map_values(const Cell* __restrict__
     bool bad = false;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        Cell c = in[i];
+        Cell c = load_cell_once(in + i);   // each cell is read once and written once
         const uint64_t v = apply_vop<V64>(op, cell_value(c, V64), a, b, table, len, bad);
         c.val = (uint32_t)v;
         if (V64) c.aux = (uint32_t)(v >> 32);
-        out[i] = c;
+        store_cell_once(out + i, c);
     }
     if (bad) atomicOr(bad_flag, 1u);
 }
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kVBlock) void k_reduce_ranges(const Group* __restri
 #pragma unroll
                 for (uint32_t u = 0; u < kRUnroll; ++u) {
                     const uint32_t e = e0 + u * kVBlock + tid;
-                    x[u] = e < nc && (uint64_t)c0 + e < S ? slots[(uint64_t)c0 + e] : Cell{0, 0, 0};
+                    x[u] = e < nc && (uint64_t)c0 + e < S ? load_cell_once(slots + c0 + e) : Cell{0, 0, 0};
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kRUnroll; ++u) {
