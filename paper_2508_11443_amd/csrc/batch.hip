@@ -377,7 +377,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                         if (dup) atomicOr(&L.dup, 1u);
                     }
                     __syncthreads();
-                    for (uint32_t p = tid; p < Z1 - Z0; p += BT) slot_pool[so + Z0 + p] = L.ent[L.smap[p]];
+                    for (uint32_t p = tid; p < Z1 - Z0; p += BT) store_cell_once(slot_pool + so + Z0 + p, L.ent[L.smap[p]]);
                 } else {
                     prefetch(K1);
                     if (s >= 2) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                             uint32_t who = first_i;
                             for (uint32_t i = 0; i < s; ++i)
                                 if (mshash(cc, bk[i].key) % s2 == p) who = i;
-                            slot_pool[so + off + p] = bk[who];
+                            store_cell_once(slot_pool + so + off + p, bk[who]);
                         }
                     }
                     if (exhausted) {
@@ -424,7 +424,8 @@ __global__ __launch_bounds__(BT) void k_batch_build(
                         h.sizes = L.sizes[gg];
                         h.t_lo = L.tsh[2 * tid];
                         h.t_hi = L.tsh[2 * tid + 1];
-                        hdr_pool[ho + gg] = h;
+                        const u32x4 hw = {h.base, h.sizes, h.t_lo, h.t_hi};
+                        __builtin_nontemporal_store(hw, reinterpret_cast<u32x4*>(hdr_pool) + ho + gg);
                     }
                 }
                 __syncthreads();
