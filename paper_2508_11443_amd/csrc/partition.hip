@@ -1,18 +1,19 @@
 // Partitioned construction: the level-one attempt as a few streaming passes.
 //
-// Buckets are cut into partitions of 1024 consecutive buckets (q = j >> 10).
-// Keys are moved into partition order by one to three coalescing radix passes
-// over q (at most 8 bits, 256 bins, per pass, so every 12288-record tile writes
-// runs of about 48 records per bin; every worker's offsets come from a scanned
-// count matrix, or from cursors on fixed-capacity regions), then every partition is finished by one workgroup that holds
-// its ~1024 keys in LDS: ranks from an LDS histogram, scan of the 128 group
-// statistics, grouping, the per-bucket level-two search of make_2, and the
-// coalesced write of the partition's contiguous cells and group headers.  Only
-// the partition totals of squared sizes (the offsets of Section 2.2, at
-// partition granularity) cross partitions: one small pass computes them, a scan
-// turns them into cell bases and the table size S.  Device-scope atomics are
-// used only to raise an attempt's outcome flags; every per-key access is a
-// coalesced stream or LDS.
+// Buckets are cut into partitions of 1024 consecutive buckets (q = j >> 10).  Keys are
+// moved into partition order by one to three coalescing radix passes over q (at most 8
+// bits, 256 bins, per pass, so every 12288-record tile writes runs of about 48 records per
+// bin); each worker's runs go to offsets from a scanned count matrix, or are reserved with
+// one atomic add per (tile, bin) on a cursor into a fixed-capacity region.  Then every
+// partition is finished by one workgroup that holds its ~1024 keys in LDS: ranks from an
+// LDS histogram, scan of the 128 group statistics, grouping, the per-bucket level-two
+// search of make_2, and the coalesced write of the partition's contiguous cells and group
+// headers.  Only the partition totals of squared sizes (the offsets of Section 2.2, at
+// partition granularity) cross partitions: either a size pass and a scan turn them into
+// cell bases and the table size S, or the final pass publishes each total and finds its
+// own base by a look-back over its predecessors'.  Device-scope atomics serve only the
+// cursors, the final pass's tickets and look-back words, and an attempt's outcome flags;
+// every per-key access is a coalesced stream or LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -553,7 +554,7 @@ __device__ __forceinline__ uint32_t min_trial_small(TriAt tri, uint32_t T, uint3
 }
 
 // waves per SIMD the final pass is compiled for (registers within 80, or 96 with an aux
-// word): the LDS of six workgroups (26.6 KB each), or five with an aux word (31.7 KB),
+// word): the LDS of six workgroups (26.5 KB each), or five with an aux word (31.5 KB),
 // fits a CU
 template <bool AUX>
 constexpr unsigned kFinalWaves = AUX ? 5u : 6u;
