@@ -397,6 +397,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the string, batched and serving measurements")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (known HBM bytes) for counter scaling")
     args = ap.parse_args()
@@ -575,8 +576,9 @@ def main():
         out["strings"] = extra_strings(dev)
         log("extra: batched build")
         out["batched"] = extra_batch(dev)
-        log("extra: serving")
-        out["serving"] = extra_serve(dev)
+        if not args.no_serving:
+            log("extra: serving")
+            out["serving"] = extra_serve(dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread)")
         out["cpu_baseline"] = cpu_leg(keys, vals, q, n, args.cpu_budget, omp=False)
