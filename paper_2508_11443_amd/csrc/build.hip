@@ -187,9 +187,9 @@ static int attempts_partitioned(fks_map* M, const uint64_t* d_keys_in, const uin
         total += (bytes_ + 255) & ~(size_t)255;
         return at;
     };
-    // two passes in the direct form reserve their runs on cursors: the records then sit in
-    // fixed-capacity regions (binsA of them after the first pass, Q after the second)
-    const bool cursor = direct && plan.passes == 2;
+    // one or two passes in the direct form reserve their runs on cursors: the records then sit
+    // in fixed-capacity regions (binsA of them after a first of two passes, Q after the last)
+    const bool cursor = direct && (plan.passes == 1 || plan.passes == 2);
     const uint64_t r1 = cursor ? std::max<uint64_t>(n, plan.cap1 * plan.binsA) : n;
     const uint64_t r2 = cursor ? std::max<uint64_t>(n, plan.capQ * Q) : n;
     const size_t o_k1 = plan.passes >= 2 ? carve(8 * r1) : 0, o_v1 = plan.passes >= 2 ? carve(4 * r1) : 0;

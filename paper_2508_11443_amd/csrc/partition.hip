@@ -1061,25 +1061,26 @@ PartPlan part_plan(uint64_t n) {
     P.bits_q = bits;
     auto clampu = [](uint64_t v, uint64_t lo, uint64_t hi) { return (uint32_t)(v < lo ? lo : v > hi ? hi : v); };
     P.W1 = clampu((n + kWorkerKeys - 1) / (kWorkerKeys), 1, 4096);
+    // regions of the cursor form: a first-level bin covers 2^shiftA partitions of 1024
+    // buckets and a partition 1024 buckets; with n keys in n buckets the keys of B buckets
+    // number B on average with a standard deviation of about sqrt(B), and the regions hold
+    // 12 deviations more (an overflow only sends the attempt back to the counted passes)
+    auto region = [](uint64_t B) {
+        const uint64_t sd = (uint64_t)std::ceil(std::sqrt((double)B));
+        return (B + 12 * sd + 64 + 255) & ~(uint64_t)255;
+    };
     if (P.Q <= 1) {
         P.passes = 0;
     } else if (bits <= 8) {
         P.passes = 1;
         P.binsA = P.Q;
+        P.capQ = region(kPartBuckets);
     } else if (bits <= 16) {
         P.passes = 2;
         P.shiftA = bits - 8;
         P.binsA = (uint32_t)((P.Q + (1u << P.shiftA) - 1) >> P.shiftA);
         P.bitsB = P.shiftA;
         P.W2 = clampu((n / P.binsA + kWorkerKeys - 1) / (kWorkerKeys), 1, 64);
-        // regions of the cursor form: a first-level bin covers 2^shiftA partitions of 1024
-        // buckets and a partition 1024 buckets; with n keys in n buckets the keys of B buckets
-        // number B on average with a standard deviation of about sqrt(B), and the regions hold
-        // 12 deviations more (an overflow only sends the attempt back to the counted passes)
-        auto region = [](uint64_t B) {
-            const uint64_t sd = (uint64_t)std::ceil(std::sqrt((double)B));
-            return (B + 12 * sd + 64 + 255) & ~(uint64_t)255;
-        };
         P.cap1 = region((uint64_t)kPartBuckets << P.shiftA);
         P.capQ = region(kPartBuckets);
     } else {
@@ -1159,6 +1160,27 @@ int part_prepare(const PartArgs& a, hipStream_t st, PartOut& o) {
     };
     if (P.passes == 0) {
         hipLaunchKernelGGL(k_set_range, 1, 64, 0, st, a.offQ, n);
+    } else if (P.passes == 1 && a.cursor) {
+        // one pass straight into the partitions' regions, each run reserved on its partition's
+        // cursor; the fused final pass's look-back words and ticket are cleared in the same launch
+        const uint64_t nzw = a.fused ? 2 * (uint64_t)P.Q : 0;
+        hipLaunchKernelGGL(k_init_cursors, grid_for_count(P.Q + nzw), 256, 0, st, a.cur1, a.begA, (uint64_t)0,
+                           (uint64_t)0, a.cur2, a.begQ, (uint64_t)P.Q, P.capQ, reinterpret_cast<uint32_t*>(a.cbase),
+                           nzw, a.fused ? a.sqQ : nullptr);
+        o.prezeroed = a.fused;
+        if (aux)
+            scatter_cursor<true>(a, a.keys, a.vals, a.aux_in, nullptr, nullptr, 0, dim3(P.W1, 1), P.W1, 0, 255, a.k2,
+                                 a.v2, a.a2, a.cur2, P.capQ, st);
+        else
+            scatter_cursor<false>(a, a.keys, a.vals, nullptr, nullptr, nullptr, 0, dim3(P.W1, 1), P.W1, 0, 255,
+                                  a.k2, a.v2, a.a2, a.cur2, P.capQ, st);
+        o.keys = a.k2;
+        o.vals = a.v2;
+        o.aux = a.a2;
+        o.aux_is_pos = aux ? 0 : 1;
+        o.qbeg = a.begQ;
+        o.qend = reinterpret_cast<const uint64_t*>(a.cur2);
+        o.qcap = P.capQ;
     } else if (P.passes == 1) {
         count(a.keys, nullptr, dim3(P.W1, 1), P.W1, 0, 255);
         scan_matrix(a, (uint64_t)kBins * P.W1, st);
