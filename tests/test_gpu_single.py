@@ -207,14 +207,15 @@ def test_bench_size_bit_exact():
     torch.cuda.empty_cache()
 
 
-def test_crowded_partition_takes_the_counted_passes():
-    """With 2^18 < n <= 2^26 keys the build reserves each partition's records in a region of
-    fixed capacity (about 1.5x the 1024 keys a partition holds on average).  Here over 2000
-    keys hash (under attempt 0's level-one constants) into the first partition's 1024
-    buckets: its region overflows and the attempt is redone with counted passes.  The table
-    must still equal the oracle's byte for byte."""
+@pytest.mark.parametrize("n", [100000, 300000])
+def test_crowded_partition_takes_the_counted_passes(n):
+    """With 1024 < n <= 2^26 keys the build reserves each partition's records in a region of
+    fixed capacity (about 1.5x the 1024 keys a partition holds on average), in one pass
+    (n = 100000) or two (n = 300000).  Here over 2000 keys hash (under attempt 0's level-one
+    constants) into the first partition's 1024 buckets: its region overflows and the attempt
+    is redone with counted passes.  The table must still equal the oracle's byte for byte."""
     from oracle import rounds, spec
-    n, seed = 300000, 0xC20D
+    seed = 0xC20D
     announce(f"gpu single u64: crowded first partition, n={n} seed={seed}")
     a0, a1, b, _ = spec.level1_consts(seed, 0)
     rng = np.random.default_rng(99)
